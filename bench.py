@@ -1,0 +1,217 @@
+"""Benchmark: direction-split exponential integrator steps on one MI355X.
+
+Default workload: 3-D advection-diffusion-reaction on 128^3, ETD2RK phisplit,
+FP64, tau = 2e-3 (A_mu = 0.02 D2 + beta_mu D1, g = u^2 (1 - u)).  A "step" is
+one full ETD2RK time step over the whole tensor (stage input with K u and g,
+two Tucker operators with the fused stage combinations), replayed from a HIP
+graph.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line with DOF-steps/s, the roofline of the dominant kernel
+(the FP64 MFMA mu-mode product) and the CPU oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF-steps/s + % of MFMA roofline, FP64 vs split-BF16 at stated rel. error"
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
+PEAK_HBM_GBS = 8000.0
+
+
+def make_workload(name: str):
+    import workloads as W
+    if name == "adr128":
+        p = W.adr_3d(n=128)
+        desc = "3-D ADR 128^3, ETD2RK phisplit, FP64, tau=2e-3"
+    elif name == "allen_cahn64":
+        p = W.allen_cahn_2d()
+        desc = "2-D Allen-Cahn 64^2, exponential Euler phisplit, FP64, tau=1e-3"
+    elif name == "nls192":
+        p = W.nls_3d(n=192)
+        desc = "3-D cubic NLS 192^3, Lawson-Euler, complex128, tau=1e-3"
+    elif name == "dr384":
+        p = W.diffusion_reaction_3d(n=384)
+        desc = "3-D diffusion-reaction 384^3, ETD2RK phisplit, FP64, tau=2e-3"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, desc
+
+
+def tucker_flops_per_step(p) -> float:
+    """Algorithmic flops of the Tucker operators of one step (2 N n_mu per real mode
+    product, 8 N n_mu per complex one)."""
+    per_tucker = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n)
+    tuckers = {"lawson_euler": 1, "exp_euler": 1, "lawson2b": 2, "etd2rk": 2}[p.scheme]
+    return tuckers * per_tucker
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="adr128")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding is described in the design notes only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2304_02327_amd as px
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p, desc = make_workload(args.workload)
+    g_param = p.g_params.get("kappa", 0.0) if p.g == "cubic_nls" else 0.0
+    plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param)
+    U0 = px.tensor_to_device(p.u0, device=dev)
+    U = U0.clone()
+    stream = torch.cuda.Stream()  # default priority
+    stream.wait_stream(torch.cuda.current_stream())
+
+    # warmup (includes the one-time graph capture)
+    with torch.cuda.stream(stream):
+        plan.run(U, args.warmup, use_graph=True, stream=stream)
+    stream.synchronize()
+    U.copy_(U0)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K graph-replayed steps
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    with torch.cuda.stream(stream):
+        plan.run(U, args.steps, use_graph=True, stream=stream)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / max(args.steps, 1)
+    value = p.N * args.steps / (gpu_ms / 1e3)
+    if not torch.isfinite(U).all():
+        raise SystemExit("non-finite state after the timed region")
+
+    # dominant kernel: the mu-mode product; time it alone with events on its stream,
+    # with the shapes and launch configuration of the step (the phi_1 Tucker)
+    ell = 1 if p.scheme in ("exp_euler", "etd2rk") else 0
+    Ms = [px.matrix_to_device(px.phi_setup(a, p.tau, ell)[ell], device=dev) for a in p.A]
+    Vk = U0.clone()
+    Wk = torch.empty_like(Vk)
+    ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64), 16),
+                     dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream)
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        for _ in range(args.kernel_reps):
+            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream)
+        k1.record(stream)
+    stream.synchronize()
+    launches = args.kernel_reps * p.d
+    avg_launch_s = k0.elapsed_time(k1) / 1e3 / launches
+    flops_per_launch = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n) / p.d
+    achieved_tf = flops_per_launch / avg_launch_s / 1e12
+    roofline = {
+        "kernel": "k_mode_product (FP64 MFMA mu-mode product)",
+        "bound": "mfma",
+        "achieved": round(achieved_tf, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
+        "traffic": None,
+        "avg_launch_us": round(avg_launch_s * 1e6, 3),
+        "flops_per_launch": flops_per_launch,
+    }
+    step_tf = tucker_flops_per_step(p) * args.steps / (gpu_ms / 1e3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if p.is_complex else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
+                   "precision": "fp64", "graph": True},
+        "wall_s_timed_region": wall,
+        "tucker_tflops_whole_step": round(step_tf, 3),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(result))
+
+
+def cpu_baseline(p, plan, U0, budget_s):
+    """The CPU FP64 oracle, timed on the host on a bounded sample of the same workload;
+    its state after the sample is also compared with the GPU's after as many steps."""
+    import numpy as np
+    import torch
+    import paper_2304_02327_amd as px
+    from oracle import schemes
+    from oracle.norms import rel_inf
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t = time.perf_counter()
+    integ = schemes.integrator_for(p)
+    setup_s = time.perf_counter() - t
+    U = np.array(p.u0)
+    t = time.perf_counter()
+    U = integ.step(U, 0.0)
+    one = time.perf_counter() - t
+    k = max(1, min(p.steps, int(math.ceil(budget_s / max(one, 1e-6)))))
+    t = time.perf_counter()
+    for i in range(1, k):
+        U = integ.step(U, i * p.tau)
+    rest = time.perf_counter() - t
+    total = one + rest
+    # the GPU state after the same k steps (direct launches)
+    Ug = U0.clone()
+    plan.run(Ug, k)
+    torch.cuda.synchronize()
+    err = rel_inf(px.tensor_from_device(Ug), U)
+    return {
+        "value": p.N * k / total,
+        "unit": "DOF-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {k} of {p.steps} steps of the same workload (oracle phi setup "
+                  f"{setup_s:.2f} s excluded); host {os.cpu_count()} logical CPUs",
+        "seconds": round(total, 3),
+        "gpu_vs_oracle_rel_inf": err,
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * expint.h -- C ABI of the direction-split ("phisplit") exponential-integrator
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper section 1, eqs. ODE and kronsum):
+ *     u'(t) = K u(t) + g(t, u(t)),   K = A_d (+) ... (+) A_1 = sum_mu I (x) .. (x) A_mu (x) .. (x) I,
+ * with u = vec(U) for an order-d tensor U of size n_1 x ... x n_d.
+ *
+ * Conventions shared by every entry point:
+ *   - Layout: tensors are stored with the first index fastest (vec() stacks
+ *     columns, section 1 after eq. tuckerexp); element (i_1,..,i_d) sits at
+ *     i_1 + n_1 (i_2 + n_2 (i_3 + ...)).  Small matrices are column-major.
+ *     Complex data is interleaved (re, im) doubles.
+ *   - Memory: pointers documented as "device" must be device memory of the
+ *     current HIP device, 16-byte aligned; "host" pointers are ordinary host
+ *     memory.  The caller owns every buffer it passes and keeps it alive until
+ *     the work on the given stream has completed.  The library never frees
+ *     caller memory.  A plan owns only its own small device copies of the
+ *     phi matrices and stencil coefficients.
+ *   - Streams: `stream` is a hipStream_t passed as void*; NULL is the legacy
+ *     default stream.  Every entry point that takes a stream only enqueues
+ *     work on it and returns without synchronising.
+ *   - Errors: every int-returning function returns EXPINT_OK (0) or a negative
+ *     status; no exception crosses the ABI.  All arguments are validated before
+ *     any work is enqueued; on error nothing has been launched.
+ *     expint_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef EXPINT_H
+#define EXPINT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define EXPINT_OK          0
+#define EXPINT_EINVAL     -1  /* invalid argument (shape, pointer, size, enum) */
+#define EXPINT_ENOMEM     -2  /* host or device allocation failed (plan creation only) */
+#define EXPINT_EHIP       -3  /* a HIP runtime call failed */
+#define EXPINT_ENOTSUP    -4  /* valid but unsupported combination */
+#define EXPINT_ENUMERIC   -5  /* non-finite input to phi_setup */
+
+/* element types of U / V / W */
+#define EXPINT_F64   0    /* double */
+#define EXPINT_C128  1    /* double complex, interleaved */
+
+/* contraction precision of the mu-mode products (phi matrices are always built in FP64) */
+#define EXPINT_PREC_FP64    0
+#define EXPINT_PREC_FP32    1   /* operands rounded to FP32, FP32 MFMA */
+#define EXPINT_PREC_BF16X3  2   /* x = hi + lo (bf16, RNE); hi*hi + hi*lo + lo*hi, FP32 accumulate */
+
+/* time-stepping schemes (paper section 2; tensor forms in section 3.2) */
+#define EXPINT_LAWSON_EULER  0  /* eq. lawsoneulertensor */
+#define EXPINT_LAWSON2B      1  /* eq. lawson2tensor */
+#define EXPINT_EXP_EULER     2  /* eq. expEulertensor, split phi_1 */
+#define EXPINT_ETD2RK        3  /* eq. ETD2RKtensor with the (l!)^{d-1} split factor of eq. dsphi */
+
+/* nonlinearities g(u) (autonomous) */
+#define EXPINT_G_NONE        0  /* g = 0 */
+#define EXPINT_G_ALLEN_CAHN  1  /* g = u - u^3 */
+#define EXPINT_G_U2_1MU      2  /* g = u^2 (1 - u) */
+#define EXPINT_G_CUBIC_NLS   3  /* g = -i kappa |u|^2 u (complex only; kappa = g_param) */
+
+/* ------------------------------------------------------------------------ */
+/* phi_setup: the small matrices phi_l(tau A) of one direction               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * phi_setup -- phi_0(tau A), ..., phi_{ell_max}(tau A) for one n x n matrix
+ * (definitions: section 1, eqs. integraldef / seriesdef; construction:
+ * section 3.1, scaling by 2^s and the squaring recurrence eq. squarephi, with
+ * a Taylor expansion of the scaled matrix in place of the quadrature).
+ *   n       >= 1
+ *   A       host, column-major, leading dimension lda >= n, float64
+ *   tau     any finite real (tau = 0 gives phi_l = I / l!)
+ *   ell_max 0..3
+ *   phi_out host, (ell_max+1) column-major n x n blocks, block l starting at
+ *           phi_out + l * ldphi * n, leading dimension ldphi >= n
+ * Returns the raw phi_l(tau A); the split factor (l!)^{d-1} is applied by the
+ * stepping code, not here.  Runs on the host CPU in FP64.
+ * Errors: EINVAL (bad sizes / NULL), ENUMERIC (non-finite entries or tau).
+ */
+int phi_setup(int n, const double* A, int lda, double tau, int ell_max,
+              double* phi_out, int ldphi);
+
+/* phi_setup_z -- complex twin of phi_setup: A and phi_out hold interleaved
+ * complex doubles (leading dimensions counted in complex elements). */
+int phi_setup_z(int n, const double* A, int lda, double tau, int ell_max,
+                double* phi_out, int ldphi);
+
+/* ------------------------------------------------------------------------ */
+/* tucker_apply: W = alpha * (V x_1 M_1 x_2 ... x_d M_d) + beta * W          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Tucker operator (section 1, eq. tuckerexp; the mu-mode product is the
+ * contraction spelled out by eq. forloop: (V x_mu M)[..i_mu..] =
+ * sum_j M[i_mu, j] V[..j..]).
+ *   d          1..4
+ *   n          host array of d sizes, n[mu] >= 1, prod n[mu] < 2^31
+ *   M          host array of d device pointers; M[mu] is an n[mu] x n[mu]
+ *              column-major matrix of the element type, or NULL for the
+ *              identity (the mode is skipped)
+ *   V          device input tensor (not modified); must not alias W
+ *   W          device output tensor
+ *   alpha,beta real scalars; beta == 0 means W is not read
+ *   dtype      EXPINT_F64 or EXPINT_C128
+ *   precision  EXPINT_PREC_FP64 (others: ENOTSUP for now)
+ *   ws         device workspace of at least tucker_workspace_size() bytes
+ *              (may be NULL when that size is 0)
+ *   stream     hipStream_t
+ * Modes are applied in the order 1..d.  Results are deterministic (no
+ * atomics, fixed reduction order).
+ */
+int tucker_apply(int d, const int* n, const void* const* M, const void* V, void* W,
+                 double alpha, double beta, int dtype, int precision,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* tucker_workspace_size -- bytes of workspace tucker_apply needs. */
+int tucker_workspace_size(int d, const int* n, int dtype, size_t* bytes);
+
+/* ------------------------------------------------------------------------ */
+/* plans and time stepping                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct expint_plan expint_plan;
+
+typedef struct expint_problem {
+  int d;                 /* 1..3 */
+  int n[4];              /* n[0..d-1] */
+  const double* A[4];    /* host, column-major n[mu] x n[mu] (complex: interleaved), lda = n[mu] */
+  double tau;            /* constant step size */
+  int scheme;            /* EXPINT_LAWSON_EULER .. EXPINT_ETD2RK */
+  int nonlin;            /* EXPINT_G_* */
+  double g_param;        /* kappa of EXPINT_G_CUBIC_NLS, unused otherwise */
+  int dtype;             /* EXPINT_F64 or EXPINT_C128 */
+  int precision;         /* EXPINT_PREC_FP64 */
+} expint_problem;
+
+/*
+ * expint_plan_create -- build the phi matrices phi_l(tau A_mu) once for every
+ * direction (section 3.1 / 4.2: computed once before the time stepping),
+ * upload them and the operator data to the current device.  Directions with
+ * bitwise-identical A share their phi.  A tridiagonal A_mu (optionally with
+ * periodic corner entries) is applied to U as a 3-point stencil; any other
+ * A_mu as a dense mu-mode product.
+ * Errors: EINVAL, ENOTSUP, ENOMEM, EHIP.  On error *plan is set to NULL.
+ */
+int expint_plan_create(expint_plan** plan, const expint_problem* prob);
+
+/* expint_plan_workspace_size -- device workspace bytes expint_step/run need. */
+int expint_plan_workspace_size(const expint_plan* plan, size_t* bytes);
+
+/*
+ * expint_plan_set_phi -- replace phi_l(tau A_mu) of direction mu (0-based)
+ * with a host matrix (column-major n[mu] x n[mu], the plan's element type),
+ * e.g. to separate contraction error from phi error in tests.  Synchronous.
+ */
+int expint_plan_set_phi(expint_plan* plan, int mu, int ell, const double* host_phi);
+
+/*
+ * expint_step -- advance U (device, in place) by one step of the plan's
+ * scheme from time t.  Enqueues a fixed kernel sequence on `stream`:
+ * stage input (K U by stencil or mu-mode products, plus g), one Tucker
+ * operator per stage with the stage combination and the next g fused into
+ * the last mu-mode product.  No allocation, so it may be graph-captured.
+ */
+int expint_step(expint_plan* plan, void* U, double t, void* ws, void* stream);
+
+/*
+ * expint_run -- nsteps >= 0 steps from t0.  use_graph != 0 captures one step
+ * into a HIP graph (once per plan / U / ws / stream combination) and replays
+ * it nsteps times; use_graph == 0 enqueues the kernels directly.
+ */
+int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
+               void* ws, void* stream);
+
+/* expint_plan_destroy -- frees the plan's device memory and graph (NULL is a no-op).
+ * The caller must make sure no enqueued work still uses the plan. */
+void expint_plan_destroy(expint_plan* plan);
+
+/* expint_last_error -- thread-local message of the last failing call ("" if none). */
+const char* expint_last_error(void);
+
+/* expint_version -- library version string. */
+const char* expint_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXPINT_H */

@@ -1,0 +1,27 @@
+"""Direction-split ("phisplit") exponential integrators on AMD MI355X.
+
+The computation lives in the C-ABI library ``libexpint.so`` (declared in
+``include/expint.h``); this package is its Python binding.  Importing it
+raises ImportError if the library has not been built.
+"""
+
+from ._binding import (  # noqa: F401
+    C128,
+    EXPORTED_SYMBOLS,
+    F64,
+    LIB_PATH,
+    NONLIN,
+    PREC_BF16X3,
+    PREC_FP32,
+    PREC_FP64,
+    SCHEMES,
+    ExpintError,
+    Plan,
+    matrix_to_device,
+    phi_setup,
+    tensor_from_device,
+    tensor_to_device,
+    tucker_apply,
+    tucker_workspace_size,
+    version,
+)

@@ -1,0 +1,282 @@
+"""ctypes binding of libexpint.so: argument marshalling only.
+
+Every computation runs in the library (host FP64 phi_setup, HIP kernels for
+everything else).  torch supplies device memory and streams.  There is no
+fallback: if the library is missing, importing this module raises.
+
+Tensor layout: a tensor with sizes n_1 x ... x n_d is a C-contiguous torch
+tensor of shape (n_d, ..., n_1) (first index fastest in memory).  A small
+matrix M (natural indices M[i, j]) lives on the device as the C-contiguous
+(n, n) tensor holding M^T, i.e. column-major M.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexpint.so")
+
+# status codes, dtypes, precisions, schemes, nonlinearities (include/expint.h)
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5
+F64, C128 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+SCHEMES = {"lawson_euler": 0, "lawson2b": 1, "exp_euler": 2, "etd2rk": 3}
+NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3}
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
+
+
+class ExpintError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"expint error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_02327_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    dp = ctypes.POINTER(c_double)
+    lib.phi_setup.argtypes = [c_int, dp, c_int, c_double, c_int, dp, c_int]
+    lib.phi_setup_z.argtypes = [c_int, dp, c_int, c_double, c_int, dp, c_int]
+    lib.tucker_apply.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
+                                 c_double, c_double, c_int, c_int, c_void_p, c_size_t, c_void_p]
+    lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, ctypes.POINTER(c_size_t)]
+    lib.expint_plan_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_void_p]
+    lib.expint_plan_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
+    lib.expint_plan_set_phi.argtypes = [c_void_p, c_int, c_int, dp]
+    lib.expint_step.argtypes = [c_void_p, c_void_p, c_double, c_void_p, c_void_p]
+    lib.expint_run.argtypes = [c_void_p, c_void_p, c_double, c_int, c_int, c_void_p, c_void_p]
+    lib.expint_plan_destroy.argtypes = [c_void_p]
+    lib.expint_plan_destroy.restype = None
+    lib.expint_last_error.restype = ctypes.c_char_p
+    lib.expint_version.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+EXPORTED_SYMBOLS = (
+    "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size",
+    "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
+    "expint_step", "expint_run", "expint_plan_destroy", "expint_last_error", "expint_version",
+)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("n", ctypes.c_int * 4),
+        ("A", ctypes.POINTER(ctypes.c_double) * 4),
+        ("tau", ctypes.c_double),
+        ("scheme", ctypes.c_int),
+        ("nonlin", ctypes.c_int),
+        ("g_param", ctypes.c_double),
+        ("dtype", ctypes.c_int),
+        ("precision", ctypes.c_int),
+    ]
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise ExpintError(rc, lib.expint_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def version() -> str:
+    return lib.expint_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# phi_setup (host)
+# ---------------------------------------------------------------------------
+
+def phi_setup(A: np.ndarray, tau: float, ell_max: int) -> List[np.ndarray]:
+    """[phi_0(tau A), ..., phi_{ell_max}(tau A)] computed by the library on the host (FP64)."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    cplx = np.iscomplexobj(A)
+    dt = np.complex128 if cplx else np.float64
+    Acm = np.asfortranarray(A, dtype=dt)  # column-major
+    out = np.zeros((ell_max + 1) * n * n, dtype=dt)
+    src = Acm.reshape(-1, order="F").view(np.float64) if cplx else Acm.reshape(-1, order="F")
+    src = np.ascontiguousarray(src)
+    dst = out.view(np.float64)
+    fn = lib.phi_setup_z if cplx else lib.phi_setup
+    _check(fn(n, _dptr(src), n, float(tau), int(ell_max), _dptr(dst), n))
+    return [out[l * n * n:(l + 1) * n * n].reshape((n, n), order="F").copy() for l in range(ell_max + 1)]
+
+
+# ---------------------------------------------------------------------------
+# device helpers
+# ---------------------------------------------------------------------------
+
+def matrix_to_device(M: np.ndarray, device="cuda"):
+    """Natural-index matrix -> device tensor holding it column-major."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(M).T)).to(device)
+
+
+def tensor_to_device(U: np.ndarray, device="cuda"):
+    """Natural-index tensor (n_1..n_d) -> device tensor in memory order (shape n_d..n_1)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(U).T)).to(device)
+
+
+def tensor_from_device(Ut) -> np.ndarray:
+    """Inverse of tensor_to_device (returns a natural-index numpy array)."""
+    return Ut.detach().cpu().numpy().T
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError(f"unsupported dtype {t.dtype} (float64 or complex128)")
+
+
+def _sizes_of(t) -> List[int]:
+    return list(reversed(t.shape))
+
+
+def _check_device_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+# ---------------------------------------------------------------------------
+# tucker_apply
+# ---------------------------------------------------------------------------
+
+def tucker_workspace_size(n: Sequence[int], dtype: int = F64) -> int:
+    d = len(n)
+    arr = (ctypes.c_int * d)(*n)
+    out = ctypes.c_size_t(0)
+    _check(lib.tucker_workspace_size(d, arr, dtype, ctypes.byref(out)))
+    return out.value
+
+
+def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
+                 precision: int = PREC_FP64, ws=None, stream=None):
+    """W = alpha * (V x_1 M_1 ... x_d M_d) + beta * W on the device (M_mu = None: identity)."""
+    import torch
+    _check_device_tensor(V, "V")
+    _check_device_tensor(W, "W")
+    n = _sizes_of(V)
+    d = len(n)
+    if len(Ms) != d:
+        raise ValueError("one matrix (or None) per mode")
+    dt = _dtype_code(V)
+    ptrs = (ctypes.c_void_p * d)()
+    for mu, M in enumerate(Ms):
+        if M is None:
+            ptrs[mu] = None
+        else:
+            _check_device_tensor(M, f"M[{mu}]")
+            if tuple(M.shape) != (n[mu], n[mu]) or M.dtype != V.dtype:
+                raise ValueError(f"M[{mu}] must be {n[mu]}x{n[mu]} of {V.dtype}")
+            ptrs[mu] = M.data_ptr()
+    need = tucker_workspace_size(n, dt)
+    if ws is None and need > 0:
+        ws = torch.empty(need, dtype=torch.uint8, device=V.device)
+    ws_ptr = ws.data_ptr() if ws is not None else None
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    arr = (ctypes.c_int * d)(*n)
+    _check(lib.tucker_apply(d, arr, ptrs, V.data_ptr(), W.data_ptr(), float(alpha), float(beta), dt,
+                            int(precision), ws_ptr, ws_bytes, _stream_handle(stream)))
+    return W
+
+
+# ---------------------------------------------------------------------------
+# plans
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """A constant-step integrator for u' = K u + g(u) on one device.
+
+    ``A`` are natural-index host matrices (numpy); ``n`` follows from them.
+    """
+
+    def __init__(self, A: Sequence[np.ndarray], tau: float, scheme: str, nonlin: str,
+                 g_param: float = 0.0, precision: str = "fp64", device="cuda"):
+        import torch
+        A = [np.asarray(a) for a in A]
+        cplx = any(np.iscomplexobj(a) for a in A) or nonlin == "cubic_nls"
+        self.dtype = C128 if cplx else F64
+        self.torch_dtype = torch.complex128 if cplx else torch.float64
+        self.n = [a.shape[0] for a in A]
+        self.d = len(A)
+        self.tau = float(tau)
+        self.device = torch.device(device)
+        npdt = np.complex128 if cplx else np.float64
+        self._host_A = [np.ascontiguousarray(np.asarray(a, dtype=npdt).T) for a in A]  # column-major
+        prob = _Problem()
+        prob.d = self.d
+        for mu in range(4):
+            prob.n[mu] = self.n[mu] if mu < self.d else 1
+        for mu in range(self.d):
+            prob.A[mu] = self._host_A[mu].view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        prob.tau = self.tau
+        prob.scheme = SCHEMES[scheme]
+        prob.nonlin = NONLIN[nonlin]
+        prob.g_param = float(g_param)
+        prob.dtype = self.dtype
+        prob.precision = PRECISIONS[precision]
+        self._handle = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(lib.expint_plan_create(ctypes.byref(self._handle), ctypes.byref(prob)))
+        size = ctypes.c_size_t(0)
+        _check(lib.expint_plan_workspace_size(self._handle, ctypes.byref(size)))
+        self.workspace_bytes = size.value
+        self.ws = torch.empty(max(self.workspace_bytes, 16), dtype=torch.uint8, device=self.device)
+
+    def set_phi(self, mu: int, ell: int, M: np.ndarray):
+        npdt = np.complex128 if self.dtype == C128 else np.float64
+        cm = np.ascontiguousarray(np.asarray(M, dtype=npdt).T).view(np.float64)
+        _check(lib.expint_plan_set_phi(self._handle, int(mu), int(ell), _dptr(cm)))
+
+    def _check_state(self, U):
+        _check_device_tensor(U, "U")
+        if _sizes_of(U) != self.n or U.dtype != self.torch_dtype:
+            raise ValueError(f"U must have sizes {self.n} (memory order) and dtype {self.torch_dtype}")
+
+    def step(self, U, t: float = 0.0, stream=None):
+        self._check_state(U)
+        _check(lib.expint_step(self._handle, U.data_ptr(), float(t), self.ws.data_ptr(), _stream_handle(stream)))
+        return U
+
+    def run(self, U, nsteps: int, t0: float = 0.0, use_graph: bool = False, stream=None):
+        self._check_state(U)
+        _check(lib.expint_run(self._handle, U.data_ptr(), float(t0), int(nsteps), 1 if use_graph else 0,
+                              self.ws.data_ptr(), _stream_handle(stream)))
+        return U
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            lib.expint_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,603 @@
+// C ABI: argument validation, plans and the per-step kernel sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace expint {
+
+namespace {
+thread_local char g_errbuf[512] = "";
+}
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_errbuf, sizeof(g_errbuf), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+namespace {
+
+size_t elem_size(int dtype) { return dtype == EXPINT_C128 ? 16 : 8; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return set_error(EXPINT_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)              \
+  do {                         \
+    int r_ = (expr);           \
+    if (r_ != EXPINT_OK) return r_; \
+  } while (0)
+
+// Tensor view of mode mu (0-based) of a d-tensor: (s, n_mu, r)
+void mode_view(int d, const int* n, int mu, long* s, long* r) {
+  long a = 1, b = 1;
+  for (int k = 0; k < mu; ++k) a *= n[k];
+  for (int k = mu + 1; k < d; ++k) b *= n[k];
+  *s = a;
+  *r = b;
+}
+
+// Tucker chain V x_1 M_1 ... x_d M_d with ping-pong buffers; the last applied
+// mode writes through `last` (its out0 and the other fields); earlier modes
+// store plainly.  Modes whose matrix is NULL are skipped.  If every matrix is
+// NULL the result is V itself, run through an identity mode-1 product is not
+// possible, so the caller must not ask for that (checked by tucker_apply).
+int tucker_chain(int dtype, int d, const int* n, const void* const* M, const void* V,
+                 void* t0, void* t1, const Epilogue& last, void* stream) {
+  int lastmu = -1;
+  for (int mu = 0; mu < d; ++mu)
+    if (M[mu]) lastmu = mu;
+  const void* src = V;
+  void* bufs[2] = {t0, t1};
+  int which = 0;
+  for (int mu = 0; mu < d; ++mu) {
+    if (!M[mu]) continue;
+    long s, r;
+    mode_view(d, n, mu, &s, &r);
+    if (mu == lastmu) {
+      TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, last, stream));
+    } else {
+      Epilogue e;
+      e.op = EPI_AXPBY;
+      e.alpha = 1.0;
+      e.beta = 0.0;
+      e.out0 = bufs[which];
+      TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, e, stream));
+      src = bufs[which];
+      which ^= 1;
+    }
+  }
+  return EXPINT_OK;
+}
+
+int count_modes(int d, const void* const* M) {
+  int c = 0;
+  for (int mu = 0; mu < d; ++mu) c += M[mu] != nullptr;
+  return c;
+}
+
+}  // namespace
+}  // namespace expint
+
+using namespace expint;
+
+// ---------------------------------------------------------------------------
+// phi_setup
+// ---------------------------------------------------------------------------
+
+extern "C" int phi_setup(int n, const double* A, int lda, double tau, int ell_max, double* phi_out,
+                         int ldphi) {
+  try {
+    return phi_setup_real(n, A, lda, tau, ell_max, phi_out, ldphi);
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "phi_setup: out of host memory");
+  }
+}
+
+extern "C" int phi_setup_z(int n, const double* A, int lda, double tau, int ell_max, double* phi_out,
+                           int ldphi) {
+  try {
+    return phi_setup_complex(n, A, lda, tau, ell_max, phi_out, ldphi);
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "phi_setup_z: out of host memory");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tucker_apply
+// ---------------------------------------------------------------------------
+
+static int validate_shape(int d, const int* n, long* N) {
+  if (d < 1 || d > 4 || !n) return set_error(EXPINT_EINVAL, "need 1 <= d <= 4 and a size array");
+  long tot = 1;
+  for (int mu = 0; mu < d; ++mu) {
+    if (n[mu] < 1) return set_error(EXPINT_EINVAL, "n[%d] = %d must be >= 1", mu, n[mu]);
+    tot *= n[mu];
+    if (tot >= (1L << 31)) return set_error(EXPINT_EINVAL, "tensor too large (prod n >= 2^31)");
+  }
+  *N = tot;
+  return EXPINT_OK;
+}
+
+extern "C" int tucker_workspace_size(int d, const int* n, int dtype, size_t* bytes) {
+  long N;
+  TRY(validate_shape(d, n, &N));
+  if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
+  if (!bytes) return set_error(EXPINT_EINVAL, "bytes is NULL");
+  const int bufs = d - 1 < 2 ? d - 1 : 2;
+  *bytes = (size_t)bufs * (size_t)N * elem_size(dtype);
+  return EXPINT_OK;
+}
+
+extern "C" int tucker_apply(int d, const int* n, const void* const* M, const void* V, void* W,
+                            double alpha, double beta, int dtype, int precision, void* ws,
+                            size_t ws_bytes, void* stream) {
+  long N;
+  TRY(validate_shape(d, n, &N));
+  if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
+  if (precision != EXPINT_PREC_FP64)
+    return set_error(EXPINT_ENOTSUP, "tucker_apply: only EXPINT_PREC_FP64 is implemented");
+  if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
+  if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
+  if (!aligned16(V) || !aligned16(W)) return set_error(EXPINT_EINVAL, "tucker_apply: V and W must be 16-byte aligned");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return set_error(EXPINT_EINVAL, "tucker_apply: alpha/beta not finite");
+  for (int mu = 0; mu < d; ++mu)
+    if (M[mu] && !aligned16(M[mu])) return set_error(EXPINT_EINVAL, "tucker_apply: M[%d] not 16-byte aligned", mu);
+  const int modes = count_modes(d, M);
+  if (modes == 0) return set_error(EXPINT_EINVAL, "tucker_apply: every M[mu] is NULL (nothing to apply)");
+  size_t need = 0;
+  {
+    const int bufs = modes - 1 < 2 ? modes - 1 : 2;
+    need = (size_t)bufs * (size_t)N * elem_size(dtype);
+  }
+  if (ws_bytes < need || (need > 0 && !ws))
+    return set_error(EXPINT_EINVAL, "tucker_apply: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (need > 0 && !aligned16(ws)) return set_error(EXPINT_EINVAL, "tucker_apply: workspace not 16-byte aligned");
+  char* w = static_cast<char*>(ws);
+  void* t0 = need ? w : nullptr;
+  void* t1 = need ? w + (size_t)N * elem_size(dtype) : nullptr;
+  Epilogue last;
+  last.op = EPI_AXPBY;
+  last.alpha = alpha;
+  last.beta = beta;
+  last.out0 = W;
+  return tucker_chain(dtype, d, n, M, V, t0, t1, last, stream);
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+struct expint_plan {
+  int d = 0;
+  int n[4] = {1, 1, 1, 1};
+  long N = 0;
+  double tau = 0.0;
+  int scheme = 0, nonlin = 0, dtype = 0, precision = 0;
+  double gparam = 0.0;
+  int ell_lo = 0, ell_hi = 0;        // phi indices the scheme uses
+  void* phi[4][3] = {};              // device phi_l(tau A_mu); shared between equal directions
+  bool phi_owner[4][3] = {};
+  bool use_stencil = false;
+  Stencil stencil;                   // device coefficient arrays when use_stencil
+  void* denseA[4] = {};              // device A_mu for the dense K u path
+  int device = 0;
+  // cached graph of one step
+  hipGraphExec_t gexec = nullptr;
+  const void* g_U = nullptr;
+  const void* g_ws = nullptr;
+  hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+int classify_tridiagonal(int n, const double* A, int cplx, bool* tri, bool* periodic) {
+  const int w = cplx ? 2 : 1;
+  auto nz = [&](int i, int j) {
+    const double* p = A + ((size_t)i + (size_t)n * j) * w;
+    return p[0] != 0.0 || (cplx && p[1] != 0.0);
+  };
+  *tri = true;
+  *periodic = false;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const int dist = i > j ? i - j : j - i;
+      if (dist <= 1 || !nz(i, j)) continue;
+      if (n >= 3 && ((i == 0 && j == n - 1) || (i == n - 1 && j == 0))) {
+        *periodic = true;
+        continue;
+      }
+      *tri = false;
+      return EXPINT_OK;
+    }
+  return EXPINT_OK;
+}
+
+void free_plan_memory(expint_plan* p) {
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int l = 0; l < 3; ++l)
+      if (p->phi_owner[mu][l] && p->phi[mu][l]) (void)hipFree(p->phi[mu][l]);
+    if (p->stencil.coef[mu]) (void)hipFree(const_cast<void*>(p->stencil.coef[mu]));
+    if (p->denseA[mu]) (void)hipFree(p->denseA[mu]);
+  }
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+}
+
+int scheme_phi_range(int scheme, int* lo, int* hi) {
+  switch (scheme) {
+    case EXPINT_LAWSON_EULER:
+    case EXPINT_LAWSON2B:
+      *lo = 0;
+      *hi = 0;
+      return EXPINT_OK;
+    case EXPINT_EXP_EULER:
+      *lo = 1;
+      *hi = 1;
+      return EXPINT_OK;
+    case EXPINT_ETD2RK:
+      *lo = 1;
+      *hi = 2;
+      return EXPINT_OK;
+    default:
+      return set_error(EXPINT_EINVAL, "unknown scheme %d", scheme);
+  }
+}
+
+int workspace_elems(const expint_plan* p, long* elems) {
+  // buffers: W (stage input), T0, T1 (Tucker ping-pong), X (U_n2 / W_b), Y (Lawson2b U_n2)
+  long k = 0;
+  switch (p->scheme) {
+    case EXPINT_LAWSON_EULER:
+    case EXPINT_EXP_EULER:
+      k = 3;
+      break;
+    case EXPINT_ETD2RK:
+      k = 4;
+      break;
+    case EXPINT_LAWSON2B:
+      k = 5;
+      break;
+  }
+  *elems = k * p->N;
+  return EXPINT_OK;
+}
+
+// stage input W = tau (K U + g(U))
+int stage_input(expint_plan* p, const void* U, void* W, hipStream_t s) {
+  if (p->use_stencil)
+    return launch_stage_stencil(p->dtype, p->stencil, p->N, U, W, p->tau, p->nonlin, p->gparam, s);
+  TRY(launch_scaled_g(p->dtype, p->N, U, W, p->tau, p->nonlin, p->gparam, s));
+  for (int mu = 0; mu < p->d; ++mu) {
+    long sv, rv;
+    mode_view(p->d, p->n, mu, &sv, &rv);
+    Epilogue e;
+    e.op = EPI_AXPBY;
+    e.alpha = p->tau;
+    e.beta = 1.0;
+    e.out0 = W;
+    TRY(launch_mode_product(p->dtype, sv, p->n[mu], rv, p->denseA[mu], U, e, s));
+  }
+  return EXPINT_OK;
+}
+
+int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
+  const size_t es = elem_size(p->dtype);
+  char* base = static_cast<char*>(ws);
+  void* W = base;
+  void* T0 = base + 1 * p->N * es;
+  void* T1 = base + 2 * p->N * es;
+  void* X = base + 3 * p->N * es;
+  void* Y = base + 4 * p->N * es;
+  const void* P0[4] = {p->phi[0][0], p->phi[1][0], p->phi[2][0], p->phi[3][0]};
+  const void* P1[4] = {p->phi[0][1], p->phi[1][1], p->phi[2][1], p->phi[3][1]};
+  const void* P2[4] = {p->phi[0][2], p->phi[1][2], p->phi[2][2], p->phi[3][2]};
+  const double split2 = std::ldexp(1.0, p->d - 1);  // (2!)^{d-1}
+  switch (p->scheme) {
+    case EXPINT_LAWSON_EULER: {
+      // U_{n+1} = (U_n + tau G_n) x_mu e^{tau A_mu}
+      TRY(launch_lawson_stage(p->dtype, p->N, U, W, nullptr, p->tau, p->nonlin, p->gparam, s));
+      Epilogue e;
+      e.op = EPI_AXPBY;
+      e.out0 = U;
+      return tucker_chain(p->dtype, p->d, p->n, P0, W, T0, T1, e, s);
+    }
+    case EXPINT_LAWSON2B: {
+      // U_n2 = (U_n + tau G_n) x e^{tau A};  U_{n+1} = (U_n + tau/2 G_n) x e^{tau A} + tau/2 G(U_n2)
+      TRY(launch_lawson_stage(p->dtype, p->N, U, W, X, p->tau, p->nonlin, p->gparam, s));
+      Epilogue e1;
+      e1.op = EPI_AXPBY;
+      e1.out0 = Y;
+      TRY(tucker_chain(p->dtype, p->d, p->n, P0, W, T0, T1, e1, s));
+      Epilogue e2;
+      e2.op = EPI_LAWSON2B_2;
+      e2.out0 = U;
+      e2.in1 = Y;
+      e2.c = 0.5 * p->tau;
+      e2.g = p->nonlin;
+      e2.gparam = p->gparam;
+      return tucker_chain(p->dtype, p->d, p->n, P0, X, T0, T1, e2, s);
+    }
+    case EXPINT_EXP_EULER: {
+      // U_{n+1} = U_n + (tau (K U_n + G_n)) x_mu phi_1(tau A_mu)   ((1!)^{d-1} = 1)
+      TRY(stage_input(p, U, W, s));
+      Epilogue e;
+      e.op = EPI_EXP_EULER;
+      e.out0 = U;
+      e.in1 = U;
+      return tucker_chain(p->dtype, p->d, p->n, P1, W, T0, T1, e, s);
+    }
+    case EXPINT_ETD2RK: {
+      // U_n2 = U_n + (tau (K U_n + G_n)) x phi_1;  W_2 = tau (G(U_n2) - G_n)
+      // U_{n+1} = U_n2 + (2!)^{d-1} W_2 x phi_2
+      TRY(stage_input(p, U, W, s));
+      Epilogue e1;
+      e1.op = EPI_ETD2RK_1;
+      e1.out0 = X;  // U_n2
+      e1.in1 = U;
+      e1.out1 = W;  // W_2 (the first stage input is no longer needed once mode 1 has read it)
+      e1.tau = p->tau;
+      e1.g = p->nonlin;
+      e1.gparam = p->gparam;
+      if (count_modes(p->d, P1) == 1) {
+        // a single mode reads W while its epilogue writes W_2: keep them apart
+        e1.out1 = T1;
+        TRY(tucker_chain(p->dtype, p->d, p->n, P1, W, T0, nullptr, e1, s));
+        W = T1;
+      } else {
+        TRY(tucker_chain(p->dtype, p->d, p->n, P1, W, T0, T1, e1, s));
+      }
+      Epilogue e2;
+      e2.op = EPI_ETD2RK_2;
+      e2.out0 = U;
+      e2.in1 = X;
+      e2.c = split2;
+      return tucker_chain(p->dtype, p->d, p->n, P2, W, T0, T1, e2, s);
+    }
+  }
+  return set_error(EXPINT_EINVAL, "unknown scheme");
+}
+
+int validate_step_args(expint_plan* p, void* U, void* ws) {
+  if (!p) return set_error(EXPINT_EINVAL, "plan is NULL");
+  if (!U || !ws) return set_error(EXPINT_EINVAL, "U and ws must be non-NULL device pointers");
+  if (!aligned16(U) || !aligned16(ws)) return set_error(EXPINT_EINVAL, "U and ws must be 16-byte aligned");
+  return EXPINT_OK;
+}
+
+}  // namespace
+
+extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob) {
+  if (!out) return set_error(EXPINT_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!prob) return set_error(EXPINT_EINVAL, "problem is NULL");
+  if (prob->d < 1 || prob->d > 3) return set_error(EXPINT_EINVAL, "d = %d: need 1 <= d <= 3", prob->d);
+  long N;
+  TRY(validate_shape(prob->d, prob->n, &N));
+  if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)
+    return set_error(EXPINT_EINVAL, "unknown dtype %d", prob->dtype);
+  if (prob->precision != EXPINT_PREC_FP64)
+    return set_error(EXPINT_ENOTSUP, "only EXPINT_PREC_FP64 stepping is implemented");
+  if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
+  const bool cplx = prob->dtype == EXPINT_C128;
+  if (cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_CUBIC_NLS)
+    return set_error(EXPINT_ENOTSUP, "complex data supports g = NONE or CUBIC_NLS");
+  if (!cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_ALLEN_CAHN &&
+      prob->nonlin != EXPINT_G_U2_1MU)
+    return set_error(EXPINT_ENOTSUP, "real data supports g = NONE, ALLEN_CAHN or U2_1MU");
+  int lo, hi;
+  TRY(scheme_phi_range(prob->scheme, &lo, &hi));
+  for (int mu = 0; mu < prob->d; ++mu)
+    if (!prob->A[mu]) return set_error(EXPINT_EINVAL, "A[%d] is NULL", mu);
+
+  expint_plan* p = new (std::nothrow) expint_plan();
+  if (!p) return set_error(EXPINT_ENOMEM, "plan allocation failed");
+  p->d = prob->d;
+  for (int mu = 0; mu < prob->d; ++mu) p->n[mu] = prob->n[mu];
+  p->N = N;
+  p->tau = prob->tau;
+  p->scheme = prob->scheme;
+  p->nonlin = prob->nonlin;
+  p->gparam = prob->g_param;
+  p->dtype = prob->dtype;
+  p->precision = prob->precision;
+  p->ell_lo = lo;
+  p->ell_hi = hi;
+  (void)hipGetDevice(&p->device);
+  const size_t es = elem_size(p->dtype);
+  int rc = EXPINT_OK;
+
+  // phi matrices: built once per distinct A_mu (section 3.1 / 4.2)
+  for (int mu = 0; mu < p->d && rc == EXPINT_OK; ++mu) {
+    const int n = p->n[mu];
+    const size_t bytes = (size_t)n * n * es;
+    int same = -1;
+    for (int nu = 0; nu < mu; ++nu)
+      if (p->n[nu] == n && std::memcmp(prob->A[nu], prob->A[mu], bytes) == 0) same = nu;
+    if (same >= 0) {
+      for (int l = lo; l <= hi; ++l) p->phi[mu][l] = p->phi[same][l];
+      continue;
+    }
+    std::vector<double> host;
+    try {
+      host.resize((size_t)(hi + 1) * n * n * (cplx ? 2 : 1));
+    } catch (const std::bad_alloc&) {
+      rc = set_error(EXPINT_ENOMEM, "host allocation for phi failed");
+      break;
+    }
+    rc = cplx ? phi_setup_complex(n, prob->A[mu], n, p->tau, hi, host.data(), n)
+              : phi_setup_real(n, prob->A[mu], n, p->tau, hi, host.data(), n);
+    for (int l = lo; l <= hi && rc == EXPINT_OK; ++l) {
+      void* dptr = nullptr;
+      if (hipMalloc(&dptr, bytes) != hipSuccess) {
+        rc = set_error(EXPINT_ENOMEM, "device allocation for phi failed");
+        break;
+      }
+      p->phi[mu][l] = dptr;
+      p->phi_owner[mu][l] = true;
+      if (hipMemcpy(dptr, host.data() + (size_t)l * n * n * (cplx ? 2 : 1), bytes, hipMemcpyHostToDevice) !=
+          hipSuccess)
+        rc = set_error(EXPINT_EHIP, "copy of phi to the device failed");
+    }
+  }
+
+  // operator data for K u: stencil if every A_mu is (periodic) tridiagonal, else dense
+  if (rc == EXPINT_OK && (p->scheme == EXPINT_EXP_EULER || p->scheme == EXPINT_ETD2RK)) {
+    bool all_tri = true;
+    bool per[4] = {false, false, false, false};
+    for (int mu = 0; mu < p->d; ++mu) {
+      bool tri, periodic;
+      classify_tridiagonal(p->n[mu], prob->A[mu], cplx, &tri, &periodic);
+      all_tri = all_tri && tri;
+      per[mu] = periodic;
+    }
+    p->use_stencil = all_tri;
+    p->stencil.d = p->d;
+    for (int mu = 0; mu < p->d && rc == EXPINT_OK; ++mu) {
+      const int n = p->n[mu];
+      const int w = cplx ? 2 : 1;
+      const double* A = prob->A[mu];
+      if (all_tri) {
+        std::vector<double> c((size_t)3 * n * w, 0.0);
+        auto put = [&](int slot, int i, int row, int col) {
+          for (int k = 0; k < w; ++k) c[((size_t)slot * n + i) * w + k] = A[((size_t)row + (size_t)n * col) * w + k];
+        };
+        for (int i = 0; i < n; ++i) {
+          put(1, i, i, i);
+          if (i > 0) put(0, i, i, i - 1);
+          if (i < n - 1) put(2, i, i, i + 1);
+        }
+        if (per[mu]) {
+          put(0, 0, 0, n - 1);
+          put(2, n - 1, n - 1, 0);
+        }
+        void* dptr = nullptr;
+        if (hipMalloc(&dptr, c.size() * sizeof(double)) != hipSuccess) {
+          rc = set_error(EXPINT_ENOMEM, "device allocation for stencil failed");
+          break;
+        }
+        p->stencil.coef[mu] = dptr;
+        p->stencil.n[mu] = n;
+        p->stencil.periodic[mu] = per[mu] ? 1 : 0;
+        if (hipMemcpy(dptr, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+          rc = set_error(EXPINT_EHIP, "copy of stencil to the device failed");
+      } else {
+        const size_t bytes = (size_t)n * n * es;
+        void* dptr = nullptr;
+        if (hipMalloc(&dptr, bytes) != hipSuccess) {
+          rc = set_error(EXPINT_ENOMEM, "device allocation for A failed");
+          break;
+        }
+        p->denseA[mu] = dptr;
+        if (hipMemcpy(dptr, A, bytes, hipMemcpyHostToDevice) != hipSuccess)
+          rc = set_error(EXPINT_EHIP, "copy of A to the device failed");
+      }
+    }
+  }
+  if (rc != EXPINT_OK) {
+    free_plan_memory(p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return EXPINT_OK;
+}
+
+extern "C" int expint_plan_workspace_size(const expint_plan* p, size_t* bytes) {
+  if (!p || !bytes) return set_error(EXPINT_EINVAL, "NULL plan or output");
+  long elems;
+  TRY(workspace_elems(p, &elems));
+  *bytes = (size_t)elems * elem_size(p->dtype);
+  return EXPINT_OK;
+}
+
+extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double* host_phi) {
+  if (!p || !host_phi) return set_error(EXPINT_EINVAL, "NULL plan or matrix");
+  if (mu < 0 || mu >= p->d) return set_error(EXPINT_EINVAL, "direction %d out of range", mu);
+  if (ell < p->ell_lo || ell > p->ell_hi)
+    return set_error(EXPINT_EINVAL, "phi_%d is not used by this scheme", ell);
+  const int n = p->n[mu];
+  const size_t bytes = (size_t)n * n * elem_size(p->dtype);
+  if (!p->phi_owner[mu][ell]) {
+    // this direction shared another direction's matrix: give it its own copy
+    void* dptr = nullptr;
+    if (hipMalloc(&dptr, bytes) != hipSuccess) return set_error(EXPINT_ENOMEM, "device allocation failed");
+    p->phi[mu][ell] = dptr;
+    p->phi_owner[mu][ell] = true;
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+  }
+  HIP_TRY(hipMemcpy(p->phi[mu][ell], host_phi, bytes, hipMemcpyHostToDevice));
+  return EXPINT_OK;
+}
+
+extern "C" int expint_step(expint_plan* p, void* U, double t, void* ws, void* stream) {
+  (void)t;  // the supported nonlinearities are autonomous
+  TRY(validate_step_args(p, U, ws));
+  return enqueue_step(p, U, ws, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int expint_run(expint_plan* p, void* U, double t0, int nsteps, int use_graph, void* ws,
+                          void* stream) {
+  (void)t0;
+  TRY(validate_step_args(p, U, ws));
+  if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps < 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!use_graph) {
+    for (int k = 0; k < nsteps; ++k) TRY(enqueue_step(p, U, ws, s));
+    return EXPINT_OK;
+  }
+  if (!s) return set_error(EXPINT_EINVAL, "graph capture needs a non-default stream");
+  if (!(p->gexec && p->g_U == U && p->g_ws == ws && p->g_stream == s)) {
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_step(p, U, ws, s);
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc != EXPINT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess) return set_error(EXPINT_EHIP, "stream capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      p->gexec = nullptr;
+      return set_error(EXPINT_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    p->g_U = U;
+    p->g_ws = ws;
+    p->g_stream = s;
+  }
+  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(p->gexec, s));
+  return EXPINT_OK;
+}
+
+extern "C" void expint_plan_destroy(expint_plan* p) {
+  if (!p) return;
+  free_plan_memory(p);
+  delete p;
+}
+
+extern "C" const char* expint_last_error(void) { return g_errbuf; }
+
+extern "C" const char* expint_version(void) { return "expint 0.1.0 (gfx950)"; }

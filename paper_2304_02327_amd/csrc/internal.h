@@ -1,0 +1,70 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/expint.h"
+
+namespace expint {
+
+// records a thread-local message and returns `code`
+int set_error(int code, const char* fmt, ...);
+
+int phi_setup_real(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
+int phi_setup_complex(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
+
+// ---------------------------------------------------------------------------
+// mu-mode product launcher
+// ---------------------------------------------------------------------------
+
+// What the last stage of a mu-mode product does with its result Y (per
+// element e of the tensor; every tensor shares the layout of Y).
+enum EpiOp : int {
+  EPI_AXPBY = 0,        // out0[e] = alpha * Y + beta * out0[e]   (beta == 0: out0 not read)
+  EPI_EXP_EULER = 1,    // out0[e] = in1[e] + Y                   (U_{n+1} = U_n + P)
+  EPI_ETD2RK_1 = 2,     // u = in1[e]; u2 = u + Y; out0[e] = u2; out1[e] = tau (g(u2) - g(u))
+  EPI_ETD2RK_2 = 3,     // out0[e] = in1[e] + c * Y
+  EPI_LAWSON2B_2 = 4,   // out0[e] = Y + c * g(in1[e])           (c = tau / 2)
+};
+
+struct Epilogue {
+  int op = EPI_AXPBY;
+  int g = EXPINT_G_NONE;
+  double alpha = 1.0, beta = 0.0, tau = 0.0, c = 0.0, gparam = 0.0;
+  void* out0 = nullptr;        // primary output (always written)
+  const void* in1 = nullptr;   // secondary input
+  void* out1 = nullptr;        // secondary output
+};
+
+// Y = V x_mu M for a tensor viewed as (s, n, r): s = prod_{nu<mu} n_nu (stride 1),
+// n = n_mu, r = prod_{nu>mu} n_nu.  M is n x n column-major (device).  The
+// epilogue decides what is stored.  dtype EXPINT_F64 or EXPINT_C128.
+int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
+                        const Epilogue& epi, void* stream);
+
+// ---------------------------------------------------------------------------
+// pointwise / stencil launchers
+// ---------------------------------------------------------------------------
+
+// Per-direction 3-point stencil coefficients on the device: lo[i] = A[i, i-1],
+// di[i] = A[i, i], up[i] = A[i, i+1]; with `periodic` the neighbours wrap
+// (lo[0] = A[0, n-1], up[n-1] = A[n-1, 0]).  Complex data: interleaved.
+struct Stencil {
+  int d = 0;
+  int n[4] = {1, 1, 1, 1};
+  const void* coef[4] = {nullptr, nullptr, nullptr, nullptr};  // 3 * n[mu] elements: lo | di | up
+  int periodic[4] = {0, 0, 0, 0};
+};
+
+// W = tau * (K U + g(U)) with K applied as the stencil.
+int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, void* W,
+                         double tau, int g, double gparam, void* stream);
+// W = a * g(U) (no K term; the dense path adds tau * U x_mu A_mu afterwards)
+int launch_scaled_g(int dtype, long N, const void* U, void* W, double a, int g, double gparam,
+                    void* stream);
+// Wa = U + tau g(U); Wb = U + tau/2 g(U) (Wb may be NULL)
+int launch_lawson_stage(int dtype, long N, const void* U, void* Wa, void* Wb, double tau, int g,
+                        double gparam, void* stream);
+
+}  // namespace expint

@@ -1,0 +1,283 @@
+// mu-mode product on FP64 MFMA (gfx950).
+//
+// The mu-mode product (section 1, eq. forloop):
+//     (V x_mu M)[i_1..i_mu..i_d] = sum_j M[i_mu, j] V[i_1..j..i_d].
+// With the tensor viewed as (s, n, r) -- s = n_1..n_{mu-1} (stride 1),
+// n = n_mu, r = n_{mu+1}..n_d -- it is a GEMM C[m, q] = sum_k Aop[m, k] Bop[k, q]:
+//   mode 1 (s == 1): m = i_1, q = the other indices;  Aop = M, Bop = V (k fastest)
+//   mode >= 2:       m = the s-index, q = i_mu, one GEMM per outer index;
+//                    Aop = V slab (m fastest), Bop = M^T (q fastest).
+// Either way Aop and the output have m as the stride-1 index, so loads and
+// stores run along contiguous memory (the non-contiguous mode is the K loop).
+//
+// Tiling: a 256-thread workgroup (4 wave64) owns a TM x TQ output tile and
+// walks K in chunks of KC, double-buffered in LDS with register prefetch of
+// the next chunk.  Each wave owns a (TM/2) x (TQ/2) sub-tile made of 16x16
+// MFMA blocks.  v_mfma_f64_16x16x4 leaves D[i][j] in lane j + 16 (i mod 4),
+// register i / 4; the B-chunk fragment is passed as the instruction's first
+// operand so that 16 consecutive output rows m land in 16 consecutive lanes
+// (128-byte store segments).  The last mode's epilogue fuses the stage
+// combination and the next stage's g.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace expint {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct GemmArgs {
+  const void* A;  // Aop[m, k] = A[m + lda k] (+ batch * sA)
+  long lda;
+  const void* B;  // Bop[k, q] = B[k bk + q bq]
+  long bk, bq;
+  long M, Q, K;
+  long sA, sC;  // batch strides of A and of the output tensors
+  long ldc;     // output element (m, q, batch) = batch * sC + m + ldc q
+  long batches, tiles_m, tiles_q;
+  Epilogue epi;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tile indices so that tiles that share an Aop block
+// (consecutive q-tiles) share that XCD's L2.
+__device__ __forceinline__ long xcd_remap(long L, long nt) {
+  constexpr long X = 8;
+  const long per = nt / X;
+  if (L >= per * X) return L;
+  return (L % X) * per + L / X;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const void* p, long i) { return static_cast<const T*>(p)[i]; }
+
+template <typename T>
+__device__ __forceinline__ void epilogue_store(const Epilogue& ep, long e, T y) {
+  T* out0 = static_cast<T*>(ep.out0);
+  switch (ep.op) {
+    case EPI_AXPBY: {
+      T v = scale(y, ep.alpha);
+      if (ep.beta != 0.0) v = add(v, scale(out0[e], ep.beta));
+      out0[e] = v;
+      break;
+    }
+    case EPI_EXP_EULER:
+      out0[e] = add(ld<T>(ep.in1, e), y);
+      break;
+    case EPI_ETD2RK_1: {
+      const T u = ld<T>(ep.in1, e);
+      const T u2 = add(u, y);
+      out0[e] = u2;
+      static_cast<T*>(ep.out1)[e] = scale(sub(g_eval(ep.g, u2, ep.gparam), g_eval(ep.g, u, ep.gparam)), ep.tau);
+      break;
+    }
+    case EPI_ETD2RK_2:
+      out0[e] = add(ld<T>(ep.in1, e), scale(y, ep.c));
+      break;
+    case EPI_LAWSON2B_2:
+      out0[e] = add(y, scale(g_eval(ep.g, ld<T>(ep.in1, e), ep.gparam), ep.c));
+      break;
+    default:
+      break;
+  }
+}
+
+template <typename T, bool BK, int TM, int TQ, int KC>
+__global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
+  constexpr bool CPLX = std::is_same<T, cdouble>::value;
+  constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
+  constexpr int LDA_S = TM;                         // LDS row stride of the A chunk
+  constexpr int LDB_S = BK ? TQ + 1 : TQ;           // padded when stored transposed
+  constexpr int WM = TM / 2, WQ = TQ / 2;
+  constexpr int FM = WM / 16, FQ = WQ / 16;
+  constexpr int AL = TM * KC / 256, BL = TQ * KC / 256;
+  static_assert(AL * 256 == TM * KC && BL * 256 == TQ * KC, "tile / thread mismatch");
+
+  __shared__ double As[2][NP][KC * LDA_S];
+  __shared__ double Bs[2][NP][KC * LDB_S];
+
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  const long T_ = xcd_remap((long)blockIdx.x, nt);
+  const long tq = T_ % g.tiles_q;
+  const long rest = T_ / g.tiles_q;
+  const long tm = rest % g.tiles_m;
+  const long b = rest / g.tiles_m;
+  const long m0 = tm * TM, q0 = tq * TQ;
+  const T* A = static_cast<const T*>(g.A) + b * g.sA;
+  const T* B = static_cast<const T*>(g.B);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave & 1) * WM, wq0 = (wave >> 1) * WQ;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  v4d acc[NP][FM][FQ];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FQ; ++j) acc[p][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  T ra[AL], rb[BL];
+  auto gload = [&](long k0) {
+#pragma unroll
+    for (int p = 0; p < AL; ++p) {
+      const int idx = tid + 256 * p;
+      const int m = idx % TM, k = idx / TM;
+      const long gm = m0 + m, gk = k0 + k;
+      ra[p] = (gm < g.M && gk < g.K) ? A[gm + g.lda * gk] : zero<T>();
+    }
+#pragma unroll
+    for (int p = 0; p < BL; ++p) {
+      const int idx = tid + 256 * p;
+      const int q = BK ? idx / KC : idx % TQ;
+      const int k = BK ? idx % KC : idx / TQ;
+      const long gq = q0 + q, gk = k0 + k;
+      rb[p] = (gq < g.Q && gk < g.K) ? B[gk * g.bk + gq * g.bq] : zero<T>();
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < AL; ++p) {
+      const int idx = tid + 256 * p;
+      const int m = idx % TM, k = idx / TM;
+      if constexpr (CPLX) {
+        As[buf][0][k * LDA_S + m] = ra[p].re;
+        As[buf][1][k * LDA_S + m] = ra[p].im;
+      } else {
+        As[buf][0][k * LDA_S + m] = ra[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BL; ++p) {
+      const int idx = tid + 256 * p;
+      const int q = BK ? idx / KC : idx % TQ;
+      const int k = BK ? idx % KC : idx / TQ;
+      if constexpr (CPLX) {
+        Bs[buf][0][k * LDB_S + q] = rb[p].re;
+        Bs[buf][1][k * LDB_S + q] = rb[p].im;
+      } else {
+        Bs[buf][0][k * LDB_S + q] = rb[p];
+      }
+    }
+  };
+
+  const int nk = (int)((g.K + KC - 1) / KC);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int cur = kc & 1;
+    if (kc + 1 < nk) gload((long)(kc + 1) * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double af[NP][FM], bf[NP][FQ];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[p][i] = As[cur][p][(kk + lk) * LDA_S + wm0 + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < FQ; ++j) bf[p][j] = Bs[cur][p][(kk + lk) * LDB_S + wq0 + j * 16 + lr];
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FQ; ++j) {
+          if constexpr (CPLX) {
+            // (Ar + i Ai)(Br + i Bi) = (Ar Br - Ai Bi) + i (Ar Bi + Ai Br)
+            acc[0][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[0][j], af[0][i], acc[0][i][j], 0, 0, 0);
+            acc[0][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bf[1][j], af[1][i], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[0][j], af[1][i], acc[1][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[1][j], af[0][i], acc[1][i][j], 0, 0, 0);
+          } else {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[0][j], af[0][i], acc[0][i][j], 0, 0, 0);
+          }
+        }
+    }
+    if (kc + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // acc[.][i][j][r] holds C[m, q] with m = wm0 + 16 i + (lane mod 16),
+  // q = wq0 + 16 j + (lane / 16) + 4 r
+  const long cbase = b * g.sC;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const long m = m0 + wm0 + i * 16 + lr;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < FQ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long q = q0 + wq0 + j * 16 + lk + 4 * r;
+        if (q >= g.Q) continue;
+        const long e = cbase + m + g.ldc * q;
+        if constexpr (CPLX)
+          epilogue_store<T>(g.epi, e, cdouble{acc[0][i][j][r], acc[1][i][j][r]});
+        else
+          epilogue_store<T>(g.epi, e, acc[0][i][j][r]);
+      }
+  }
+}
+
+template <typename T, bool BK, int TM, int TQ, int KC>
+int launch_tile(GemmArgs& g, hipStream_t s) {
+  g.tiles_m = (g.M + TM - 1) / TM;
+  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  if (nt <= 0) return EXPINT_OK;
+  if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
+  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC>), dim3((unsigned)nt), dim3(256), 0, s, g);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
+  return EXPINT_OK;
+}
+
+}  // namespace
+
+int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
+                        const Epilogue& epi, void* stream) {
+  if (s <= 0 || n <= 0 || r <= 0) return EXPINT_OK;
+  GemmArgs g;
+  g.epi = epi;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool cplx = dtype == EXPINT_C128;
+  if (s == 1) {
+    // C[i, c] = sum_j M[i, j] V[j, c]; Aop = M, Bop = V (k fastest)
+    g.A = M;
+    g.lda = n;
+    g.B = V;
+    g.bk = 1;
+    g.bq = n;
+    g.M = n;
+    g.Q = r;
+    g.K = n;
+    g.sA = 0;
+    g.sC = 0;
+    g.ldc = n;
+    g.batches = 1;
+    return cplx ? launch_tile<cdouble, true, 64, 64, 8>(g, st) : launch_tile<double, true, 64, 64, 16>(g, st);
+  }
+  // per outer index b: C[a, i] = sum_j V[a, j, b] M[i, j]; Aop = V slab, Bop = M^T
+  g.A = V;
+  g.lda = s;
+  g.B = M;
+  g.bk = n;
+  g.bq = 1;
+  g.M = s;
+  g.Q = n;
+  g.K = n;
+  g.sA = s * (long)n;
+  g.sC = s * (long)n;
+  g.ldc = s;
+  g.batches = r;
+  return cplx ? launch_tile<cdouble, false, 64, 64, 8>(g, st) : launch_tile<double, false, 64, 64, 16>(g, st);
+}
+
+}  // namespace expint
