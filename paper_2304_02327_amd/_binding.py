@@ -37,6 +37,10 @@ class ExpintError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7) as
+    # /opt/rocm's.  Loading torch first makes this library bind to that one
+    # runtime, so device pointers and streams from torch are valid here.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_02327_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)

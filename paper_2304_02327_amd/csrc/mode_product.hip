@@ -20,6 +20,8 @@
 // combination and the next stage's g.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "device_common.h"
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
   constexpr int FM = WM / 16, FQ = WQ / 16;
   constexpr int AL = TM * KC / 256, BL = TQ * KC / 256;
   static_assert(AL * 256 == TM * KC && BL * 256 == TQ * KC, "tile / thread mismatch");
+  static_assert(FM >= 1 && FQ >= 1 && KC % 4 == 0, "tile too small");
 
   __shared__ double As[2][NP][KC * LDA_S];
   __shared__ double Bs[2][NP][KC * LDB_S];
@@ -124,14 +127,19 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
 #pragma unroll
       for (int j = 0; j < FQ; ++j) acc[p][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  T ra[AL], rb[BL];
-  auto gload = [&](long k0) {
+  // global -> registers for one K chunk.  The load always happens, from a
+  // clamped in-range address; values outside the matrix are replaced by zero
+  // only when the chunk is written to LDS.  With no branch around the loads
+  // and no use of their values until then, the compiler counts outstanding
+  // loads exactly (vmcnt) and two chunks stay in flight.
+  const long Mlast = g.M - 1, Qlast = g.Q - 1, Klast = g.K - 1;
+  auto gload = [&](T (&ra)[AL], T (&rb)[BL], long k0) {
 #pragma unroll
     for (int p = 0; p < AL; ++p) {
       const int idx = tid + 256 * p;
       const int m = idx % TM, k = idx / TM;
       const long gm = m0 + m, gk = k0 + k;
-      ra[p] = (gm < g.M && gk < g.K) ? A[gm + g.lda * gk] : zero<T>();
+      ra[p] = A[(gm < Mlast ? gm : Mlast) + g.lda * (gk < Klast ? gk : Klast)];
     }
 #pragma unroll
     for (int p = 0; p < BL; ++p) {
@@ -139,19 +147,22 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
       const int q = BK ? idx / KC : idx % TQ;
       const int k = BK ? idx % KC : idx / TQ;
       const long gq = q0 + q, gk = k0 + k;
-      rb[p] = (gq < g.Q && gk < g.K) ? B[gk * g.bk + gq * g.bq] : zero<T>();
+      rb[p] = B[(gk < Klast ? gk : Klast) * g.bk + (gq < Qlast ? gq : Qlast) * g.bq];
     }
   };
-  auto sstore = [&](int buf) {
+  // registers -> LDS buffer `buf` (complex data split into real and imaginary planes)
+  auto sstore = [&](const T (&ra)[AL], const T (&rb)[BL], long k0, int buf) {
 #pragma unroll
     for (int p = 0; p < AL; ++p) {
       const int idx = tid + 256 * p;
       const int m = idx % TM, k = idx / TM;
+      const bool ok = m0 + m <= Mlast && k0 + k <= Klast;
+      const T v = ok ? ra[p] : zero<T>();
       if constexpr (CPLX) {
-        As[buf][0][k * LDA_S + m] = ra[p].re;
-        As[buf][1][k * LDA_S + m] = ra[p].im;
+        As[buf][0][k * LDA_S + m] = v.re;
+        As[buf][1][k * LDA_S + m] = v.im;
       } else {
-        As[buf][0][k * LDA_S + m] = ra[p];
+        As[buf][0][k * LDA_S + m] = v;
       }
     }
 #pragma unroll
@@ -159,22 +170,17 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
       const int idx = tid + 256 * p;
       const int q = BK ? idx / KC : idx % TQ;
       const int k = BK ? idx % KC : idx / TQ;
+      const bool ok = q0 + q <= Qlast && k0 + k <= Klast;
+      const T v = ok ? rb[p] : zero<T>();
       if constexpr (CPLX) {
-        Bs[buf][0][k * LDB_S + q] = rb[p].re;
-        Bs[buf][1][k * LDB_S + q] = rb[p].im;
+        Bs[buf][0][k * LDB_S + q] = v.re;
+        Bs[buf][1][k * LDB_S + q] = v.im;
       } else {
-        Bs[buf][0][k * LDB_S + q] = rb[p];
+        Bs[buf][0][k * LDB_S + q] = v;
       }
     }
   };
-
-  const int nk = (int)((g.K + KC - 1) / KC);
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) {
-    const int cur = kc & 1;
-    if (kc + 1 < nk) gload((long)(kc + 1) * KC);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       double af[NP][FM], bf[NP][FQ];
@@ -200,8 +206,37 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
           }
         }
     }
-    if (kc + 1 < nk) sstore(cur ^ 1);
+  };
+
+  // Two register sets keep two K chunks in flight: while LDS buffer c is
+  // consumed, chunk k+1 travels into the other register set and chunk k+2 is
+  // requested.  Loads inside the steady-state loop are unconditional (a chunk
+  // past the end reads clamped addresses and is masked to zero), so the
+  // outstanding-load count is the same on every path and the compiler waits
+  // only for the chunk it is about to store.  One barrier per chunk.
+  const int nk = (int)((g.K + KC - 1) / KC);
+  T ra0[AL], rb0[BL], ra1[AL], rb1[BL];
+  gload(ra0, rb0, 0);
+  gload(ra1, rb1, KC);
+  sstore(ra0, rb0, 0, 0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 2 < nk; kc += 2) {
+    gload(ra0, rb0, (long)(kc + 2) * KC);
+    compute(0);
+    sstore(ra1, rb1, (long)(kc + 1) * KC, 1);
     __syncthreads();
+    gload(ra1, rb1, (long)(kc + 3) * KC);
+    compute(1);
+    sstore(ra0, rb0, (long)(kc + 2) * KC, 0);
+    __syncthreads();
+  }
+  // tail: one or two chunks left; buffer 0 holds chunk kc, ra1 chunk kc + 1
+  compute(0);
+  if (kc + 1 < nk) {
+    sstore(ra1, rb1, (long)(kc + 1) * KC, 1);
+    __syncthreads();
+    compute(1);
   }
 
   // acc[.][i][j][r] holds C[m, q] with m = wm0 + 16 i + (lane mod 16),
@@ -239,6 +274,43 @@ int launch_tile(GemmArgs& g, hipStream_t s) {
   return EXPINT_OK;
 }
 
+// Tile shapes: TM x TQ outputs per 256-thread workgroup.  Smaller tiles give
+// more workgroups (more independent load chains per CU) on small tensors;
+// larger tiles more reuse per loaded byte on large ones.  EXPINT_TILE
+// (e.g. "64x32") overrides the choice.
+enum Tile { T64x64 = 0, T64x32 = 1, T32x64 = 2, T128x64 = 3, T64x128 = 4, T32x32 = 5 };
+
+int tile_override() {
+  const char* e = std::getenv("EXPINT_TILE");
+  if (!e) return -1;
+  const char* names[] = {"64x64", "64x32", "32x64", "128x64", "64x128", "32x32"};
+  for (int i = 0; i < 6; ++i)
+    if (std::strcmp(e, names[i]) == 0) return i;
+  return -1;
+}
+
+int choose_tile(long M, long Q, long batches) {
+  const int o = tile_override();
+  if (o >= 0) return o;
+  const long t64 = ((M + 63) / 64) * ((Q + 63) / 64) * batches;  // 64x64 tiles
+  if (t64 >= 8 * 256 && M >= 128) return T128x64;
+  if (t64 >= 4 * 256) return T64x64;
+  return T64x32;
+}
+
+template <typename T, bool BK>
+int launch_choice(GemmArgs& g, hipStream_t st) {
+  constexpr int KCR = std::is_same<T, cdouble>::value ? 8 : 16;
+  switch (choose_tile(g.M, g.Q, g.batches)) {
+    case T64x32: return launch_tile<T, BK, 64, 32, KCR>(g, st);
+    case T32x64: return launch_tile<T, BK, 32, 64, KCR>(g, st);
+    case T128x64: return launch_tile<T, BK, 128, 64, KCR>(g, st);
+    case T64x128: return launch_tile<T, BK, 64, 128, KCR>(g, st);
+    case T32x32: return launch_tile<T, BK, 32, 32, KCR * 2>(g, st);
+    default: return launch_tile<T, BK, 64, 64, KCR>(g, st);
+  }
+}
+
 }  // namespace
 
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
@@ -262,7 +334,7 @@ int launch_mode_product(int dtype, long s, int n, long r, const void* M, const v
     g.sC = 0;
     g.ldc = n;
     g.batches = 1;
-    return cplx ? launch_tile<cdouble, true, 64, 64, 8>(g, st) : launch_tile<double, true, 64, 64, 16>(g, st);
+    return cplx ? launch_choice<cdouble, true>(g, st) : launch_choice<double, true>(g, st);
   }
   // per outer index b: C[a, i] = sum_j V[a, j, b] M[i, j]; Aop = V slab, Bop = M^T
   g.A = V;
@@ -277,7 +349,7 @@ int launch_mode_product(int dtype, long s, int n, long r, const void* M, const v
   g.sC = s * (long)n;
   g.ldc = s;
   g.batches = r;
-  return cplx ? launch_tile<cdouble, false, 64, 64, 8>(g, st) : launch_tile<double, false, 64, 64, 16>(g, st);
+  return cplx ? launch_choice<cdouble, false>(g, st) : launch_choice<double, false>(g, st);
 }
 
 }  // namespace expint

@@ -26,28 +26,36 @@ struct StencilArgs {
   double gparam;
 };
 
-template <typename T>
+// One thread per element.  N < 2^31, so 32-bit index arithmetic is exact; the
+// direction count D is a template parameter so the direction loop unrolls.
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
-  const long e = (long)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= a.N) return;
+  const unsigned e = blockIdx.x * (unsigned)kThreads + threadIdx.x;
+  if (e >= (unsigned)a.N) return;
   const T* U = static_cast<const T*>(a.U);
   const T u = U[e];
   T acc = zero<T>();
-  long rem = e, stride = 1;
-  for (int mu = 0; mu < a.d; ++mu) {
-    const int nm = a.n[mu];
-    const int i = (int)(rem % nm);
-    rem /= nm;
+  unsigned rem = e, stride = 1;
+#pragma unroll
+  for (int mu = 0; mu < D; ++mu) {
+    const unsigned nm = (unsigned)a.n[mu];
+    unsigned i;
+    if (mu < D - 1) {
+      i = rem % nm;
+      rem /= nm;
+    } else {
+      i = rem;
+    }
     const T* c = static_cast<const T*>(a.coef[mu]);
     acc = fma_t(c[nm + i], u, acc);
     if (i > 0)
       acc = fma_t(c[i], U[e - stride], acc);
     else if (a.periodic[mu])
-      acc = fma_t(c[i], U[e + (long)(nm - 1) * stride], acc);
-    if (i < nm - 1)
+      acc = fma_t(c[i], U[e + (nm - 1) * stride], acc);
+    if (i + 1 < nm)
       acc = fma_t(c[2 * nm + i], U[e + stride], acc);
     else if (a.periodic[mu])
-      acc = fma_t(c[2 * nm + i], U[e - (long)(nm - 1) * stride], acc);
+      acc = fma_t(c[2 * nm + i], U[e - (nm - 1) * stride], acc);
     stride *= nm;
   }
   static_cast<T*>(a.W)[e] = scale(add(acc, g_eval(a.g, u, a.gparam)), a.tau);
@@ -99,10 +107,24 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
   a.g = g;
   a.gparam = gparam;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dtype == EXPINT_C128)
-    hipLaunchKernelGGL(k_stage_stencil<cdouble>, dim3(blocks_for(N)), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_stage_stencil<double>, dim3(blocks_for(N)), dim3(kThreads), 0, s, a);
+  const dim3 grid(blocks_for(N)), block(kThreads);
+  const bool c = dtype == EXPINT_C128;
+  switch (st.d) {
+    case 1:
+      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 1>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_stage_stencil<double, 1>), grid, block, 0, s, a);
+      break;
+    case 2:
+      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 2>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_stage_stencil<double, 2>), grid, block, 0, s, a);
+      break;
+    case 3:
+      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 3>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_stage_stencil<double, 3>), grid, block, 0, s, a);
+      break;
+    default:
+      return set_error(EXPINT_ENOTSUP, "stencil: d = %d not supported", st.d);
+  }
   return check_launch("stage_stencil");
 }
 

@@ -145,3 +145,16 @@ def test_plan_create_rejects_bad_problems():
     prob.precision = 2
     assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
     assert B.lib.expint_step(None, None, 0.0, None, None) == B.EINVAL
+
+
+def test_single_hip_runtime_in_process():
+    """The library must share torch's HIP runtime (one libamdhip64 mapped), otherwise
+    torch's device pointers and streams are foreign to it."""
+    import subprocess
+    import sys
+    code = ("import os, paper_2304_02327_amd;"
+            "m = open('/proc/%d/maps' % os.getpid()).read();"
+            "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "1", out.stdout + out.stderr

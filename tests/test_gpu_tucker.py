@@ -90,3 +90,12 @@ def test_rejects_aliasing_and_short_workspace():
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(px.ExpintError):
         px.tucker_apply(Ms, V, W, ws=ws)
+
+
+@pytest.mark.parametrize("tile", ["64x64", "64x32", "32x64", "128x64", "64x128", "32x32"])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_every_tile_shape(tile, cplx, monkeypatch):
+    """Each tile shape the launcher can pick (forced through EXPINT_TILE) on ragged sizes."""
+    monkeypatch.setenv("EXPINT_TILE", tile)
+    got, ref = _run((37, 70, 133), seed=90, cplx=cplx)
+    assert rel_inf(got, ref) <= TOL
