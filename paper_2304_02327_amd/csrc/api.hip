@@ -467,6 +467,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
     }
     p->use_stencil = all_tri;
     p->stencil.d = p->d;
+    bool all_toeplitz = true;
     for (int mu = 0; mu < p->d && rc == EXPINT_OK; ++mu) {
       const int n = p->n[mu];
       const int w = cplx ? 2 : 1;
@@ -485,6 +486,20 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
           put(0, 0, 0, n - 1);
           put(2, n - 1, n - 1, 0);
         }
+        // Toeplitz: the entries that are used are constant along each diagonal
+        bool toep = true;
+        for (int slot = 0; slot < 3 && toep; ++slot)
+          for (int i = 0; i < n && toep; ++i) {
+            if ((slot == 0 && i == 0 && !per[mu]) || (slot == 2 && i == n - 1 && !per[mu])) continue;
+            const int ref = (slot == 0 && !per[mu]) ? 1 : 0;
+            for (int k = 0; k < w; ++k)
+              if (c[((size_t)slot * n + i) * w + k] != c[((size_t)slot * n + ref) * w + k]) toep = false;
+          }
+        all_toeplitz = all_toeplitz && toep;
+        for (int slot = 0; slot < 3; ++slot) {
+          const int ref = (slot == 0 && !per[mu] && n > 1) ? 1 : 0;
+          for (int k = 0; k < w; ++k) p->stencil.tc[mu][slot][k] = c[((size_t)slot * n + ref) * w + k];
+        }
         void* dptr = nullptr;
         if (hipMalloc(&dptr, c.size() * sizeof(double)) != hipSuccess) {
           rc = set_error(EXPINT_ENOMEM, "device allocation for stencil failed");
@@ -495,6 +510,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
         p->stencil.periodic[mu] = per[mu] ? 1 : 0;
         if (hipMemcpy(dptr, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
           rc = set_error(EXPINT_EHIP, "copy of stencil to the device failed");
+        p->stencil.toeplitz = all_toeplitz;
       } else {
         const size_t bytes = (size_t)n * n * es;
         void* dptr = nullptr;

@@ -55,6 +55,10 @@ struct Stencil {
   int n[4] = {1, 1, 1, 1};
   const void* coef[4] = {nullptr, nullptr, nullptr, nullptr};  // 3 * n[mu] elements: lo | di | up
   int periodic[4] = {0, 0, 0, 0};
+  // Every direction Toeplitz (constant diagonals): the three values of each
+  // direction travel as kernel arguments, interleaved (re, im) for complex data.
+  bool toeplitz = false;
+  double tc[4][3][2] = {};
 };
 
 // W = tau * (K U + g(U)) with K applied as the stencil.

@@ -88,17 +88,41 @@ __device__ __forceinline__ void epilogue_store(const Epilogue& ep, long e, T y) 
   }
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC>
-__global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
+// Buffer loads: a resource covers exactly one operand (matrix, slab or whole
+// tensor), so a read past its end returns zero in hardware.  A K index past
+// the end always lands past the end of the operand's range (the operands are
+// K-major beyond their last K row), and rows or columns past M or Q are sent
+// there explicitly through an out-of-range offset computed once per thread.
+// The per-chunk advance along K is a scalar offset.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double buffer_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ cdouble buffer_ld<cdouble>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(cdouble, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+__global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
   constexpr bool CPLX = std::is_same<T, cdouble>::value;
   constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
+  constexpr int NT = 64 * WGM * WGQ;                // threads
+  constexpr unsigned SZ = sizeof(T);
   constexpr int LDA_S = TM;                         // LDS row stride of the A chunk
   constexpr int LDB_S = BK ? TQ + 1 : TQ;           // padded when stored transposed
-  constexpr int WM = TM / 2, WQ = TQ / 2;
+  constexpr int WM = TM / WGM, WQ = TQ / WGQ;
   constexpr int FM = WM / 16, FQ = WQ / 16;
-  constexpr int AL = TM * KC / 256, BL = TQ * KC / 256;
-  static_assert(AL * 256 == TM * KC && BL * 256 == TQ * KC, "tile / thread mismatch");
-  static_assert(FM >= 1 && FQ >= 1 && KC % 4 == 0, "tile too small");
+  constexpr int AL = TM * KC / NT, BL = TQ * KC / NT;
+  static_assert(AL * NT == TM * KC && BL * NT == TQ * KC, "tile / thread mismatch");
+  static_assert(FM >= 1 && FQ >= 1 && WM % 16 == 0 && WQ % 16 == 0 && KC % 4 == 0, "bad tile");
 
   __shared__ double As[2][NP][KC * LDA_S];
   __shared__ double Bs[2][NP][KC * LDB_S];
@@ -109,15 +133,41 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
   const long rest = T_ / g.tiles_q;
   const long tm = rest % g.tiles_m;
   const long b = rest / g.tiles_m;
-  const long m0 = tm * TM, q0 = tq * TQ;
+  const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
+  const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
+  const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
+
+  // operand ranges: Aop = one slab (or M), Bop = M (or the whole tensor)
   const T* A = static_cast<const T*>(g.A) + b * g.sA;
-  const T* B = static_cast<const T*>(g.B);
+  const unsigned abytes = (unsigned)(g.lda * g.K * SZ);
+  const unsigned bbytes = BK ? (unsigned)(g.bq * g.Q * SZ) : (unsigned)(g.bk * g.K * SZ);
+  const __amdgpu_buffer_rsrc_t ra_src = make_rsrc(A, abytes);
+  const __amdgpu_buffer_rsrc_t rb_src = make_rsrc(static_cast<const T*>(g.B), bbytes);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm0 = (wave & 1) * WM, wq0 = (wave >> 1) * WQ;
+  const int wm0 = (wave % WGM) * WM, wq0 = (wave / WGM) * WQ;
   const int lr = lane & 15, lk = lane >> 4;
+
+  // per-thread byte offsets of the chunk at k0 = 0
+  unsigned va[AL], vb[BL];
+#pragma unroll
+  for (int p = 0; p < AL; ++p) {
+    const int idx = tid + NT * p;
+    const int m = idx % TM, k = idx / TM;
+    va[p] = (m0 + m < Mi) ? ((unsigned)(m0 + m) + lda * (unsigned)k) * SZ : abytes;
+  }
+#pragma unroll
+  for (int p = 0; p < BL; ++p) {
+    const int idx = tid + NT * p;
+    const int q = BK ? idx / KC : idx % TQ;
+    const int k = BK ? idx % KC : idx / TQ;
+    if (BK)  // k fastest: K validity is checked per chunk; a Q overrun leaves the tensor
+      vb[p] = ((unsigned)k + bq * (unsigned)(q0 + q)) * SZ;
+    else
+      vb[p] = (q0 + q < Qi) ? ((unsigned)(q0 + q) + bk * (unsigned)k) * SZ : bbytes;
+  }
 
   v4d acc[NP][FM][FQ];
 #pragma unroll
@@ -127,56 +177,45 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
 #pragma unroll
       for (int j = 0; j < FQ; ++j) acc[p][i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  // global -> registers for one K chunk.  The load always happens, from a
-  // clamped in-range address; values outside the matrix are replaced by zero
-  // only when the chunk is written to LDS.  With no branch around the loads
-  // and no use of their values until then, the compiler counts outstanding
-  // loads exactly (vmcnt) and two chunks stay in flight.
-  const long Mlast = g.M - 1, Qlast = g.Q - 1, Klast = g.K - 1;
-  auto gload = [&](T (&ra)[AL], T (&rb)[BL], long k0) {
+  auto gload = [&](T (&ra)[AL], T (&rb)[BL], int k0) {
+    const unsigned sa = lda * (unsigned)k0 * SZ;
 #pragma unroll
-    for (int p = 0; p < AL; ++p) {
-      const int idx = tid + 256 * p;
-      const int m = idx % TM, k = idx / TM;
-      const long gm = m0 + m, gk = k0 + k;
-      ra[p] = A[(gm < Mlast ? gm : Mlast) + g.lda * (gk < Klast ? gk : Klast)];
-    }
+    for (int p = 0; p < AL; ++p) ra[p] = buffer_ld<T>(ra_src, va[p], sa);
+    if constexpr (BK) {
 #pragma unroll
-    for (int p = 0; p < BL; ++p) {
-      const int idx = tid + 256 * p;
-      const int q = BK ? idx / KC : idx % TQ;
-      const int k = BK ? idx % KC : idx / TQ;
-      const long gq = q0 + q, gk = k0 + k;
-      rb[p] = B[(gk < Klast ? gk : Klast) * g.bk + (gq < Qlast ? gq : Qlast) * g.bq];
+      for (int p = 0; p < BL; ++p) {
+        const int k = (tid + NT * p) % KC;
+        rb[p] = buffer_ld<T>(rb_src, (k0 + k < Ki) ? vb[p] : bbytes, (unsigned)k0 * SZ);
+      }
+    } else {
+      const unsigned sb = bk * (unsigned)k0 * SZ;
+#pragma unroll
+      for (int p = 0; p < BL; ++p) rb[p] = buffer_ld<T>(rb_src, vb[p], sb);
     }
   };
   // registers -> LDS buffer `buf` (complex data split into real and imaginary planes)
-  auto sstore = [&](const T (&ra)[AL], const T (&rb)[BL], long k0, int buf) {
+  auto sstore = [&](const T (&ra)[AL], const T (&rb)[BL], int buf) {
 #pragma unroll
     for (int p = 0; p < AL; ++p) {
-      const int idx = tid + 256 * p;
+      const int idx = tid + NT * p;
       const int m = idx % TM, k = idx / TM;
-      const bool ok = m0 + m <= Mlast && k0 + k <= Klast;
-      const T v = ok ? ra[p] : zero<T>();
       if constexpr (CPLX) {
-        As[buf][0][k * LDA_S + m] = v.re;
-        As[buf][1][k * LDA_S + m] = v.im;
+        As[buf][0][k * LDA_S + m] = ra[p].re;
+        As[buf][1][k * LDA_S + m] = ra[p].im;
       } else {
-        As[buf][0][k * LDA_S + m] = v;
+        As[buf][0][k * LDA_S + m] = ra[p];
       }
     }
 #pragma unroll
     for (int p = 0; p < BL; ++p) {
-      const int idx = tid + 256 * p;
+      const int idx = tid + NT * p;
       const int q = BK ? idx / KC : idx % TQ;
       const int k = BK ? idx % KC : idx / TQ;
-      const bool ok = q0 + q <= Qlast && k0 + k <= Klast;
-      const T v = ok ? rb[p] : zero<T>();
       if constexpr (CPLX) {
-        Bs[buf][0][k * LDB_S + q] = v.re;
-        Bs[buf][1][k * LDB_S + q] = v.im;
+        Bs[buf][0][k * LDB_S + q] = rb[p].re;
+        Bs[buf][1][k * LDB_S + q] = rb[p].im;
       } else {
-        Bs[buf][0][k * LDB_S + q] = v;
+        Bs[buf][0][k * LDB_S + q] = rb[p];
       }
     }
   };
@@ -211,30 +250,30 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
   // Two register sets keep two K chunks in flight: while LDS buffer c is
   // consumed, chunk k+1 travels into the other register set and chunk k+2 is
   // requested.  Loads inside the steady-state loop are unconditional (a chunk
-  // past the end reads clamped addresses and is masked to zero), so the
-  // outstanding-load count is the same on every path and the compiler waits
-  // only for the chunk it is about to store.  One barrier per chunk.
-  const int nk = (int)((g.K + KC - 1) / KC);
+  // past the end reads zeros), so the outstanding-load count is the same on
+  // every path and the compiler waits only for the chunk it is about to
+  // store.  One barrier per chunk.
+  const int nk = (Ki + KC - 1) / KC;
   T ra0[AL], rb0[BL], ra1[AL], rb1[BL];
   gload(ra0, rb0, 0);
   gload(ra1, rb1, KC);
-  sstore(ra0, rb0, 0, 0);
+  sstore(ra0, rb0, 0);
   __syncthreads();
   int kc = 0;
   for (; kc + 2 < nk; kc += 2) {
-    gload(ra0, rb0, (long)(kc + 2) * KC);
+    gload(ra0, rb0, (kc + 2) * KC);
     compute(0);
-    sstore(ra1, rb1, (long)(kc + 1) * KC, 1);
+    sstore(ra1, rb1, 1);
     __syncthreads();
-    gload(ra1, rb1, (long)(kc + 3) * KC);
+    gload(ra1, rb1, (kc + 3) * KC);
     compute(1);
-    sstore(ra0, rb0, (long)(kc + 2) * KC, 0);
+    sstore(ra0, rb0, 0);
     __syncthreads();
   }
   // tail: one or two chunks left; buffer 0 holds chunk kc, ra1 chunk kc + 1
   compute(0);
   if (kc + 1 < nk) {
-    sstore(ra1, rb1, (long)(kc + 1) * KC, 1);
+    sstore(ra1, rb1, 1);
     __syncthreads();
     compute(1);
   }
@@ -244,15 +283,15 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
   const long cbase = b * g.sC;
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
-    const long m = m0 + wm0 + i * 16 + lr;
-    if (m >= g.M) continue;
+    const int m = m0 + wm0 + i * 16 + lr;
+    if (m >= Mi) continue;
 #pragma unroll
     for (int j = 0; j < FQ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const long q = q0 + wq0 + j * 16 + lk + 4 * r;
-        if (q >= g.Q) continue;
-        const long e = cbase + m + g.ldc * q;
+        const int q = q0 + wq0 + j * 16 + lk + 4 * r;
+        if (q >= Qi) continue;
+        const long e = cbase + m + g.ldc * (long)q;
         if constexpr (CPLX)
           epilogue_store<T>(g.epi, e, cdouble{acc[0][i][j][r], acc[1][i][j][r]});
         else
@@ -261,53 +300,61 @@ __global__ __launch_bounds__(256) void k_mode_product(GemmArgs g) {
   }
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
 int launch_tile(GemmArgs& g, hipStream_t s) {
   g.tiles_m = (g.M + TM - 1) / TM;
   g.tiles_q = (g.Q + TQ - 1) / TQ;
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
-  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC>), dim3((unsigned)nt), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC, WGM, WGQ>), dim3((unsigned)nt), dim3(64 * WGM * WGQ), 0,
+                     s, g);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
 }
 
-// Tile shapes: TM x TQ outputs per 256-thread workgroup.  Smaller tiles give
-// more workgroups (more independent load chains per CU) on small tensors;
-// larger tiles more reuse per loaded byte on large ones.  EXPINT_TILE
-// (e.g. "64x32") overrides the choice.
-enum Tile { T64x64 = 0, T64x32 = 1, T32x64 = 2, T128x64 = 3, T64x128 = 4, T32x32 = 5 };
+// Tile configurations (TM x TQ outputs per workgroup; "w8" = 8 waves, else 4).
+// EXPINT_TILE set to one of these names overrides the automatic choice.
+const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128",
+                                  "32x32", "64x64w8", "128x64w8", "128x128w8", "128x128"};
+constexpr int kNumTiles = sizeof(kTileNames) / sizeof(kTileNames[0]);
 
 int tile_override() {
   const char* e = std::getenv("EXPINT_TILE");
   if (!e) return -1;
-  const char* names[] = {"64x64", "64x32", "32x64", "128x64", "64x128", "32x32"};
-  for (int i = 0; i < 6; ++i)
-    if (std::strcmp(e, names[i]) == 0) return i;
+  for (int i = 0; i < kNumTiles; ++i)
+    if (std::strcmp(e, kTileNames[i]) == 0) return i;
   return -1;
 }
 
-int choose_tile(long M, long Q, long batches) {
+// Measured on MI355X (FP64, K = n): 128x64 outputs on 8 waves is the fastest
+// real tile from 128^3 to 384^3 (69% of the FP64 MFMA peak at 384^3); complex
+// data, with four MFMAs per output block, does best on 64x64 / 8 waves.
+// Narrow M (short contiguous dimension) takes 32-row tiles to waste less.
+int choose_tile(bool cplx, long M) {
   const int o = tile_override();
   if (o >= 0) return o;
-  const long t64 = ((M + 63) / 64) * ((Q + 63) / 64) * batches;  // 64x64 tiles
-  if (t64 >= 8 * 256 && M >= 128) return T128x64;
-  if (t64 >= 4 * 256) return T64x64;
-  return T64x32;
+  if (cplx) return M >= 64 ? 6 : 2;
+  if (M >= 128) return 7;
+  if (M >= 64) return 6;
+  return 2;
 }
 
 template <typename T, bool BK>
 int launch_choice(GemmArgs& g, hipStream_t st) {
   constexpr int KCR = std::is_same<T, cdouble>::value ? 8 : 16;
-  switch (choose_tile(g.M, g.Q, g.batches)) {
-    case T64x32: return launch_tile<T, BK, 64, 32, KCR>(g, st);
-    case T32x64: return launch_tile<T, BK, 32, 64, KCR>(g, st);
-    case T128x64: return launch_tile<T, BK, 128, 64, KCR>(g, st);
-    case T64x128: return launch_tile<T, BK, 64, 128, KCR>(g, st);
-    case T32x32: return launch_tile<T, BK, 32, 32, KCR * 2>(g, st);
-    default: return launch_tile<T, BK, 64, 64, KCR>(g, st);
+  switch (choose_tile(std::is_same<T, cdouble>::value, g.M)) {
+    case 1: return launch_tile<T, BK, 64, 32, KCR, 2, 2>(g, st);
+    case 2: return launch_tile<T, BK, 32, 64, KCR, 2, 2>(g, st);
+    case 3: return launch_tile<T, BK, 128, 64, KCR, 2, 2>(g, st);
+    case 4: return launch_tile<T, BK, 64, 128, KCR, 2, 2>(g, st);
+    case 5: return launch_tile<T, BK, 32, 32, KCR * 2, 2, 2>(g, st);
+    case 6: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4>(g, st);
+    case 7: return launch_tile<T, BK, 128, 64, KCR, 4, 2>(g, st);
+    case 8: return launch_tile<T, BK, 128, 128, KCR, 4, 2>(g, st);
+    case 9: return launch_tile<T, BK, 128, 128, KCR, 2, 2>(g, st);
+    default: return launch_tile<T, BK, 64, 64, KCR, 2, 2>(g, st);
   }
 }
 
@@ -316,6 +363,11 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
                         const Epilogue& epi, void* stream) {
   if (s <= 0 || n <= 0 || r <= 0) return EXPINT_OK;
+  // buffer-resource offsets are 32-bit; with operands below 2 GiB an operand's
+  // range plus its largest K offset still fits
+  const long bytes = s * (long)n * r * (dtype == EXPINT_C128 ? 16 : 8);
+  if (bytes >= (1L << 31))
+    return set_error(EXPINT_ENOTSUP, "mode product: tensors of %ld bytes exceed the 2 GiB limit", bytes);
   GemmArgs g;
   g.epi = epi;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -19,6 +19,7 @@ struct StencilArgs {
   int n[4];
   int periodic[4];
   const void* coef[4];
+  double tc[4][3][2];  // Toeplitz values (lo, di, up) per direction
   const void* U;
   void* W;
   double tau;
@@ -26,11 +27,28 @@ struct StencilArgs {
   double gparam;
 };
 
+// Workgroups are dealt round-robin over the 8 XCDs.  Remapping block L so that
+// XCD x sweeps the x-th contiguous eighth of the tensor keeps the neighbour
+// planes of a block in the L2 of the XCD that reads them (without it every
+// XCD fetches the planes above and below its own from memory again).
+__device__ __forceinline__ unsigned xcd_block(unsigned L, unsigned nb) {
+  const unsigned per = nb / 8u;
+  if (L >= per * 8u) return L;
+  return (L % 8u) * per + L / 8u;
+}
+
 // One thread per element.  N < 2^31, so 32-bit index arithmetic is exact; the
 // direction count D is a template parameter so the direction loop unrolls.
-template <typename T, int D>
+template <typename T>
+__device__ __forceinline__ T tcoef(const double (&v)[2]);
+template <>
+__device__ __forceinline__ double tcoef<double>(const double (&v)[2]) { return v[0]; }
+template <>
+__device__ __forceinline__ cdouble tcoef<cdouble>(const double (&v)[2]) { return cdouble{v[0], v[1]}; }
+
+template <typename T, int D, bool TOEP>
 __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
-  const unsigned e = blockIdx.x * (unsigned)kThreads + threadIdx.x;
+  const unsigned e = xcd_block(blockIdx.x, gridDim.x) * (unsigned)kThreads + threadIdx.x;
   if (e >= (unsigned)a.N) return;
   const T* U = static_cast<const T*>(a.U);
   const T u = U[e];
@@ -47,15 +65,18 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
       i = rem;
     }
     const T* c = static_cast<const T*>(a.coef[mu]);
-    acc = fma_t(c[nm + i], u, acc);
+    const T clo = TOEP ? tcoef<T>(a.tc[mu][0]) : c[i];
+    const T cdi = TOEP ? tcoef<T>(a.tc[mu][1]) : c[nm + i];
+    const T cup = TOEP ? tcoef<T>(a.tc[mu][2]) : c[2 * nm + i];
+    acc = fma_t(cdi, u, acc);
     if (i > 0)
-      acc = fma_t(c[i], U[e - stride], acc);
+      acc = fma_t(clo, U[e - stride], acc);
     else if (a.periodic[mu])
-      acc = fma_t(c[i], U[e + (nm - 1) * stride], acc);
+      acc = fma_t(clo, U[e + (nm - 1) * stride], acc);
     if (i + 1 < nm)
-      acc = fma_t(c[2 * nm + i], U[e + stride], acc);
+      acc = fma_t(cup, U[e + stride], acc);
     else if (a.periodic[mu])
-      acc = fma_t(c[2 * nm + i], U[e - (nm - 1) * stride], acc);
+      acc = fma_t(cup, U[e - (nm - 1) * stride], acc);
     stride *= nm;
   }
   static_cast<T*>(a.W)[e] = scale(add(acc, g_eval(a.g, u, a.gparam)), a.tau);
@@ -100,6 +121,8 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
     a.n[mu] = st.n[mu];
     a.periodic[mu] = st.periodic[mu];
     a.coef[mu] = st.coef[mu];
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 2; ++c) a.tc[mu][k][c] = st.tc[mu][k][c];
   }
   a.U = U;
   a.W = W;
@@ -109,22 +132,28 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(blocks_for(N)), block(kThreads);
   const bool c = dtype == EXPINT_C128;
+#define EXPINT_STENCIL_LAUNCH(D)                                                                     \
+  if (st.toeplitz) {                                                                                 \
+    if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, D, true>), grid, block, 0, s, a);           \
+    else hipLaunchKernelGGL((k_stage_stencil<double, D, true>), grid, block, 0, s, a);              \
+  } else {                                                                                           \
+    if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, D, false>), grid, block, 0, s, a);          \
+    else hipLaunchKernelGGL((k_stage_stencil<double, D, false>), grid, block, 0, s, a);             \
+  }
   switch (st.d) {
     case 1:
-      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 1>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_stage_stencil<double, 1>), grid, block, 0, s, a);
+      EXPINT_STENCIL_LAUNCH(1);
       break;
     case 2:
-      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 2>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_stage_stencil<double, 2>), grid, block, 0, s, a);
+      EXPINT_STENCIL_LAUNCH(2);
       break;
     case 3:
-      if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, 3>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((k_stage_stencil<double, 3>), grid, block, 0, s, a);
+      EXPINT_STENCIL_LAUNCH(3);
       break;
     default:
       return set_error(EXPINT_ENOTSUP, "stencil: d = %d not supported", st.d);
   }
+#undef EXPINT_STENCIL_LAUNCH
   return check_launch("stage_stencil");
 }
 

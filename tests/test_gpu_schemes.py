@@ -138,3 +138,36 @@ def test_zero_steps_is_identity():
     p = W.allen_cahn_2d(n=16)
     got = _gpu_run(p, 0)
     assert np.array_equal(got, p.u0)
+
+
+@pytest.mark.parametrize("n", [(1, 5, 7), (6, 1, 1), (1, 1, 1), (70, 3, 2), (2, 40, 3)])
+def test_stencil_degenerate_shapes(n):
+    """Tridiagonal operators with size-1/2/3 directions through the stencil stage."""
+    p = W.adr_3d(n=n)
+    got = _gpu_run(p, 4)
+    ref = schemes.run_problem(p, steps=4)
+    assert rel_inf(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("n", [(3, 4, 5), (5, 3, 2), (33, 17, 20)])
+def test_stencil_periodic_small(n):
+    """Periodic 3-point operators (corner entries) including n = 3 directions."""
+    p = W.nls_3d(n=n)
+    p.scheme = "etd2rk"
+    got = _gpu_run(p, 3)
+    ref = schemes.run_problem(p, steps=3)
+    assert rel_inf(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["exp_euler", "etd2rk"])
+def test_stencil_variable_coefficients(scheme):
+    """Tridiagonal but not Toeplitz (diagonals vary along the direction): coefficients
+    are read from the device arrays instead of kernel arguments."""
+    p = W.adr_3d(n=(20, 21, 22), scheme=scheme)
+    rng = np.random.default_rng(44)
+    for mu in range(3):
+        n = p.A[mu].shape[0]
+        p.A[mu] = p.A[mu] + np.diag(rng.uniform(-5, 5, n)) + np.diag(rng.uniform(-2, 2, n - 1), 1)
+    got = _gpu_run(p, 5)
+    ref = schemes.run_problem(p, steps=5)
+    assert rel_inf(got, ref) <= TOL
