@@ -47,6 +47,41 @@ def make_workload(name: str):
     return p, desc
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mode_product_adr128_hbm_traffic.md")
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per mu-mode-product launch from the committed PMC summary, or None when
+    the workload differs or the kernel source changed since the counters were taken."""
+    import hashlib
+    if workload != "adr128" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            fields[k] = v
+    src = os.path.join(ROOT, fields.get("kernel_source", "missing"))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernel_source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def calibrate_copy():
+    """A plain copy kernel of known size: reads and writes 512 MiB per launch, so the
+    FETCH_SIZE / WRITE_SIZE counters it produces give their scale factor."""
+    import torch
+    n = 512 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 5}))
+
+
 def tucker_flops_per_step(p) -> float:
     """Algorithmic flops of the Tucker operators of one step (2 N n_mu per real mode
     product, 8 N n_mu per complex one)."""
@@ -64,7 +99,12 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 512 MiB five times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(sharding is described in the design notes only).", file=sys.stderr)
@@ -138,7 +178,9 @@ def main():
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(args.workload),
+        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes_per_launch": 2 * (16 if p.is_complex else 8) * p.N,
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
         "flops_per_launch": flops_per_launch,
     }
