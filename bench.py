@@ -25,6 +25,8 @@ if ROOT not in sys.path:
 
 METRIC = "DOF-steps/s + % of MFMA roofline, FP64 vs split-BF16 at stated rel. error"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2516.6  # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0
 
 
@@ -97,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="adr128")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="contraction precision of the mu-mode products (state and phi stay FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -118,7 +122,7 @@ def main():
     torch.cuda.set_device(dev)
     p, desc = make_workload(args.workload)
     g_param = p.g_params.get("kappa", 0.0) if p.g == "cubic_nls" else 0.0
-    plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param)
+    plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param, precision=args.precision)
     U0 = px.tensor_to_device(p.u0, device=dev)
     U = U0.clone()
     stream = torch.cuda.Stream()  # default priority
@@ -158,32 +162,59 @@ def main():
     ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64), 16),
                      dtype=torch.uint8, device=dev)
     with torch.cuda.stream(stream):
+        prec_code = {"fp64": px.PREC_FP64, "fp32": px.PREC_FP32, "bf16x3": px.PREC_BF16X3}[args.precision]
         for _ in range(3):
-            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream)
+            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
         k0 = torch.cuda.Event(enable_timing=True)
         k1 = torch.cuda.Event(enable_timing=True)
         k0.record(stream)
         for _ in range(args.kernel_reps):
-            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream)
+            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
         k1.record(stream)
     stream.synchronize()
     launches = args.kernel_reps * p.d
     avg_launch_s = k0.elapsed_time(k1) / 1e3 / launches
     flops_per_launch = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n) / p.d
     achieved_tf = flops_per_launch / avg_launch_s / 1e12
-    roofline = {
-        "kernel": "k_mode_product (FP64 MFMA mu-mode product)",
-        "bound": "mfma",
-        "achieved": round(achieved_tf, 3),
-        "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
-        "traffic": measured_traffic(args.workload),
+    esz = 16 if p.is_complex else 8
+    if args.precision == "fp64":
+        alg_bytes = 2 * esz * p.N
+        roofline = {
+            "kernel": "k_mode_product (FP64 MFMA mu-mode product)",
+            "bound": "mfma",
+            "achieved": round(achieved_tf, 3),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
+            "traffic": measured_traffic(args.workload),
+        }
+    else:
+        # a reduced-precision Tucker reads FP64, keeps FP32 intermediates, writes FP64:
+        # d modes move (8 + 4) + (4 + 4) (d - 2) + (4 + 8) bytes per element in total
+        tot = (12 + 8 * (p.d - 2) + 12) if p.d >= 2 else 16
+        alg_bytes = tot * p.N / p.d
+        gbs = alg_bytes / avg_launch_s / 1e9
+        hw_mult = 1 if args.precision == "fp32" else 3
+        peak_c = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS
+        intensity = hw_mult * flops_per_launch / alg_bytes
+        ridge = peak_c * 1e12 / (PEAK_HBM_GBS * 1e9)
+        if intensity < ridge:
+            roofline = {"kernel": f"k_mode_product_{args.precision} ({args.precision} mu-mode product)",
+                        "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}
+        else:
+            hw_tf = hw_mult * achieved_tf
+            roofline = {"kernel": f"k_mode_product_{args.precision} ({args.precision} mu-mode product)",
+                        "bound": "mfma", "achieved": round(hw_tf, 3), "peak": peak_c, "unit": "TFLOP/s",
+                        "frac": round(hw_tf / peak_c, 4), "traffic": None}
+        roofline["algorithmic_tflops_fp64_equivalent"] = round(achieved_tf, 3)
+        roofline["hardware_flop_multiplier"] = hw_mult
+    roofline.update({
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "algorithmic_bytes_per_launch": 2 * (16 if p.is_complex else 8) * p.N,
+        "algorithmic_bytes_per_launch": alg_bytes,
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
         "flops_per_launch": flops_per_launch,
-    }
+    })
     step_tf = tucker_flops_per_step(p) * args.steps / (gpu_ms / 1e3) / 1e12
 
     result = {
@@ -197,15 +228,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if p.is_complex else "f64",
+        "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
+                 {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
-                   "precision": "fp64", "graph": True},
+                   "precision": args.precision, "graph": True},
         "wall_s_timed_region": wall,
         "tucker_tflops_whole_step": round(step_tf, 3),
         "roofline": roofline,
     }
 
+    if args.precision != "fp64":
+        # error of the reduced-precision run against the FP64 path after the same steps
+        ref_plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param)
+        Uref = U0.clone()
+        ref_plan.run(Uref, args.steps)
+        torch.cuda.synchronize()
+        d = (U - Uref).abs().max().item() / Uref.abs().max().item()
+        result["rel_err_vs_fp64"] = d
+        ref_plan.close()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
     plan.close()

@@ -57,12 +57,18 @@ void mode_view(int d, const int* n, int mu, long* s, long* r) {
 // store plainly.  Modes whose matrix is NULL are skipped.  If every matrix is
 // NULL the result is V itself, run through an identity mode-1 product is not
 // possible, so the caller must not ask for that (checked by tucker_apply).
-int tucker_chain(int dtype, int d, const int* n, const void* const* M, const void* V,
+//
+// With a reduced contraction precision the inner modes keep FP32
+// intermediates in the ping-pong buffers (half the bytes of FP64) and the
+// last mode returns to FP64 through its epilogue.
+int tucker_chain(int dtype, int precision, int d, const int* n, const void* const* M, const void* V,
                  void* t0, void* t1, const Epilogue& last, void* stream) {
   int lastmu = -1;
   for (int mu = 0; mu < d; ++mu)
     if (M[mu]) lastmu = mu;
+  const bool lp = precision != EXPINT_PREC_FP64;
   const void* src = V;
+  bool src32 = false;
   void* bufs[2] = {t0, t1};
   int which = 0;
   for (int mu = 0; mu < d; ++mu) {
@@ -70,19 +76,30 @@ int tucker_chain(int dtype, int d, const int* n, const void* const* M, const voi
     long s, r;
     mode_view(d, n, mu, &s, &r);
     if (mu == lastmu) {
-      TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, last, stream));
+      if (lp)
+        TRY(launch_mode_product_lp(precision, src32, false, s, n[mu], r, M[mu], src, last, stream));
+      else
+        TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, last, stream));
     } else {
       Epilogue e;
       e.op = EPI_AXPBY;
       e.alpha = 1.0;
       e.beta = 0.0;
       e.out0 = bufs[which];
-      TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, e, stream));
+      if (lp)
+        TRY(launch_mode_product_lp(precision, src32, true, s, n[mu], r, M[mu], src, e, stream));
+      else
+        TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, e, stream));
       src = bufs[which];
+      src32 = lp;
       which ^= 1;
     }
   }
   return EXPINT_OK;
+}
+
+bool valid_precision(int precision) {
+  return precision == EXPINT_PREC_FP64 || precision == EXPINT_PREC_FP32 || precision == EXPINT_PREC_BF16X3;
 }
 
 int count_modes(int d, const void* const* M) {
@@ -150,8 +167,9 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   long N;
   TRY(validate_shape(d, n, &N));
   if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
-  if (precision != EXPINT_PREC_FP64)
-    return set_error(EXPINT_ENOTSUP, "tucker_apply: only EXPINT_PREC_FP64 is implemented");
+  if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "tucker_apply: unknown precision %d", precision);
+  if (precision != EXPINT_PREC_FP64 && dtype != EXPINT_F64)
+    return set_error(EXPINT_ENOTSUP, "tucker_apply: reduced precision is implemented for real data only");
   if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
   if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
   if (!aligned16(V) || !aligned16(W)) return set_error(EXPINT_EINVAL, "tucker_apply: V and W must be 16-byte aligned");
@@ -176,7 +194,7 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   last.alpha = alpha;
   last.beta = beta;
   last.out0 = W;
-  return tucker_chain(dtype, d, n, M, V, t0, t1, last, stream);
+  return tucker_chain(dtype, precision, d, n, M, V, t0, t1, last, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,7 +332,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       Epilogue e;
       e.op = EPI_AXPBY;
       e.out0 = U;
-      return tucker_chain(p->dtype, p->d, p->n, P0, W, T0, T1, e, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e, s);
     }
     case EXPINT_LAWSON2B: {
       // U_n2 = (U_n + tau G_n) x e^{tau A};  U_{n+1} = (U_n + tau/2 G_n) x e^{tau A} + tau/2 G(U_n2)
@@ -322,7 +340,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       Epilogue e1;
       e1.op = EPI_AXPBY;
       e1.out0 = Y;
-      TRY(tucker_chain(p->dtype, p->d, p->n, P0, W, T0, T1, e1, s));
+      TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e1, s));
       Epilogue e2;
       e2.op = EPI_LAWSON2B_2;
       e2.out0 = U;
@@ -330,7 +348,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e2.c = 0.5 * p->tau;
       e2.g = p->nonlin;
       e2.gparam = p->gparam;
-      return tucker_chain(p->dtype, p->d, p->n, P0, X, T0, T1, e2, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, X, T0, T1, e2, s);
     }
     case EXPINT_EXP_EULER: {
       // U_{n+1} = U_n + (tau (K U_n + G_n)) x_mu phi_1(tau A_mu)   ((1!)^{d-1} = 1)
@@ -339,7 +357,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e.op = EPI_EXP_EULER;
       e.out0 = U;
       e.in1 = U;
-      return tucker_chain(p->dtype, p->d, p->n, P1, W, T0, T1, e, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e, s);
     }
     case EXPINT_ETD2RK: {
       // U_n2 = U_n + (tau (K U_n + G_n)) x phi_1;  W_2 = tau (G(U_n2) - G_n)
@@ -356,17 +374,17 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       if (count_modes(p->d, P1) == 1) {
         // a single mode reads W while its epilogue writes W_2: keep them apart
         e1.out1 = T1;
-        TRY(tucker_chain(p->dtype, p->d, p->n, P1, W, T0, nullptr, e1, s));
+        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, nullptr, e1, s));
         W = T1;
       } else {
-        TRY(tucker_chain(p->dtype, p->d, p->n, P1, W, T0, T1, e1, s));
+        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e1, s));
       }
       Epilogue e2;
       e2.op = EPI_ETD2RK_2;
       e2.out0 = U;
       e2.in1 = X;
       e2.c = split2;
-      return tucker_chain(p->dtype, p->d, p->n, P2, W, T0, T1, e2, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P2, W, T0, T1, e2, s);
     }
   }
   return set_error(EXPINT_EINVAL, "unknown scheme");
@@ -390,8 +408,9 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   TRY(validate_shape(prob->d, prob->n, &N));
   if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)
     return set_error(EXPINT_EINVAL, "unknown dtype %d", prob->dtype);
-  if (prob->precision != EXPINT_PREC_FP64)
-    return set_error(EXPINT_ENOTSUP, "only EXPINT_PREC_FP64 stepping is implemented");
+  if (!valid_precision(prob->precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", prob->precision);
+  if (prob->precision != EXPINT_PREC_FP64 && prob->dtype != EXPINT_F64)
+    return set_error(EXPINT_ENOTSUP, "reduced contraction precision is implemented for real data only");
   if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
   const bool cplx = prob->dtype == EXPINT_C128;
   if (cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_CUBIC_NLS)

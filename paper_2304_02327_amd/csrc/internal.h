@@ -43,6 +43,12 @@ struct Epilogue {
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
                         const Epilogue& epi, void* stream);
 
+// Reduced-precision contraction (EXPINT_PREC_FP32 / EXPINT_PREC_BF16X3) of a real
+// mu-mode product: V is FP32 when v32 (else FP64), M is FP64; with out32 the
+// result is stored plainly as FP32 into epi.out0, else it runs the FP64 epilogue.
+int launch_mode_product_lp(int precision, bool v32, bool out32, long s, int n, long r, const void* M,
+                           const void* V, const Epilogue& epi, void* stream);
+
 // ---------------------------------------------------------------------------
 // pointwise / stencil launchers
 // ---------------------------------------------------------------------------

@@ -405,3 +405,424 @@ int launch_mode_product(int dtype, long s, int n, long r, const void* M, const v
 }
 
 }  // namespace expint
+
+// ===========================================================================
+// Reduced-precision contractions of the same mu-mode product.
+//
+// The phi matrices and the state stay FP64; only the contraction is done in
+// lower precision (the paper names single and half precision as future work
+// for GPU runs, section 5).  Two variants, both with FP32 accumulation:
+//   FP32    operands rounded to FP32, v_mfma_f32_16x16x4f32;
+//   BF16X3  x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest
+//           even), x*y ~ hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16.
+// Inner modes write FP32 intermediates; the last mode converts its FP32
+// result to FP64 and runs the FP64 epilogue.  For both MFMAs D[i][j] sits in
+// lane j + 16 (i / 4), register i mod 4 (probed on the device), so with the
+// B fragment as first operand the 16 lanes of a row group hold 16
+// consecutive outputs m.
+// ===========================================================================
+namespace expint {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <typename T>
+__device__ __forceinline__ T buffer_ld_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double buffer_ld_s<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ float buffer_ld_s<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+struct GemmArgsLP {
+  GemmArgs g;      // shapes, strides, epilogue (out0 is float* when out32)
+};
+
+template <bool OUT32>
+__device__ __forceinline__ void lp_store(const Epilogue& ep, long e, float y) {
+  if constexpr (OUT32)
+    static_cast<float*>(ep.out0)[e] = y;
+  else
+    epilogue_store<double>(ep, e, (double)y);
+}
+
+// ---------------------------------------------------------------------------
+// FP32: structure of the FP64 kernel with an FP32 LDS and f32 MFMA
+// ---------------------------------------------------------------------------
+template <typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+__global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g) {
+  constexpr int NT = 64 * WGM * WGQ;
+  constexpr unsigned SA = sizeof(TA), SB = sizeof(TB);
+  constexpr int LDA_S = TM, LDB_S = BK ? TQ + 1 : TQ;
+  constexpr int WM = TM / WGM, WQ = TQ / WGQ;
+  constexpr int FM = WM / 16, FQ = WQ / 16;
+  constexpr int AL = TM * KC / NT, BL = TQ * KC / NT;
+  static_assert(AL * NT == TM * KC && BL * NT == TQ * KC, "tile / thread mismatch");
+  static_assert(FM >= 1 && FQ >= 1 && KC % 4 == 0, "bad tile");
+  __shared__ float As[2][KC * LDA_S];
+  __shared__ float Bs[2][KC * LDB_S];
+
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  const long T_ = xcd_remap((long)blockIdx.x, nt);
+  const long tq = T_ % g.tiles_q, rest = T_ / g.tiles_q;
+  const long tm = rest % g.tiles_m, b = rest / g.tiles_m;
+  const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
+  const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
+  const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
+  const TA* A = static_cast<const TA*>(g.A) + b * g.sA;
+  const unsigned abytes = (unsigned)(g.lda * g.K * SA);
+  const unsigned bbytes = BK ? (unsigned)(g.bq * g.Q * SB) : (unsigned)(g.bk * g.K * SB);
+  const __amdgpu_buffer_rsrc_t ra_src = make_rsrc(A, abytes);
+  const __amdgpu_buffer_rsrc_t rb_src = make_rsrc(static_cast<const TB*>(g.B), bbytes);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % WGM) * WM, wq0 = (wave / WGM) * WQ;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  unsigned va[AL], vb[BL];
+#pragma unroll
+  for (int p = 0; p < AL; ++p) {
+    const int idx = tid + NT * p, m = idx % TM, k = idx / TM;
+    va[p] = (m0 + m < Mi) ? ((unsigned)(m0 + m) + lda * (unsigned)k) * SA : abytes;
+  }
+#pragma unroll
+  for (int p = 0; p < BL; ++p) {
+    const int idx = tid + NT * p;
+    const int q = BK ? idx / KC : idx % TQ, k = BK ? idx % KC : idx / TQ;
+    if (BK)
+      vb[p] = ((unsigned)k + bq * (unsigned)(q0 + q)) * SB;
+    else
+      vb[p] = (q0 + q < Qi) ? ((unsigned)(q0 + q) + bk * (unsigned)k) * SB : bbytes;
+  }
+  v4f acc[FM][FQ];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FQ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto gload = [&](TA (&ra)[AL], TB (&rb)[BL], int k0) {
+    const unsigned sa = lda * (unsigned)k0 * SA;
+#pragma unroll
+    for (int p = 0; p < AL; ++p) ra[p] = buffer_ld_s<TA>(ra_src, va[p], sa);
+    if constexpr (BK) {
+#pragma unroll
+      for (int p = 0; p < BL; ++p) {
+        const int k = (tid + NT * p) % KC;
+        rb[p] = buffer_ld_s<TB>(rb_src, (k0 + k < Ki) ? vb[p] : bbytes, (unsigned)k0 * SB);
+      }
+    } else {
+      const unsigned sb = bk * (unsigned)k0 * SB;
+#pragma unroll
+      for (int p = 0; p < BL; ++p) rb[p] = buffer_ld_s<TB>(rb_src, vb[p], sb);
+    }
+  };
+  auto sstore = [&](const TA (&ra)[AL], const TB (&rb)[BL], int buf) {
+#pragma unroll
+    for (int p = 0; p < AL; ++p) {
+      const int idx = tid + NT * p, m = idx % TM, k = idx / TM;
+      As[buf][k * LDA_S + m] = (float)ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BL; ++p) {
+      const int idx = tid + NT * p;
+      const int q = BK ? idx / KC : idx % TQ, k = BK ? idx % KC : idx / TQ;
+      Bs[buf][k * LDB_S + q] = (float)rb[p];
+    }
+  };
+  auto compute = [&](int cur) {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      float af[FM], bf[FQ];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = As[cur][(kk + lk) * LDA_S + wm0 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < FQ; ++j) bf[j] = Bs[cur][(kk + lk) * LDB_S + wq0 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FQ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[j], af[i], acc[i][j], 0, 0, 0);
+    }
+  };
+  const int nk = (Ki + KC - 1) / KC;
+  TA ra0[AL], ra1[AL];
+  TB rb0[BL], rb1[BL];
+  gload(ra0, rb0, 0);
+  gload(ra1, rb1, KC);
+  sstore(ra0, rb0, 0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 2 < nk; kc += 2) {
+    gload(ra0, rb0, (kc + 2) * KC);
+    compute(0);
+    sstore(ra1, rb1, 1);
+    __syncthreads();
+    gload(ra1, rb1, (kc + 3) * KC);
+    compute(1);
+    sstore(ra0, rb0, 0);
+    __syncthreads();
+  }
+  compute(0);
+  if (kc + 1 < nk) {
+    sstore(ra1, rb1, 1);
+    __syncthreads();
+    compute(1);
+  }
+  // acc[i][j][r]: m = wm0 + 16 i + (lane mod 16), q = wq0 + 16 j + 4 (lane / 16) + r
+  const long cbase = b * g.sC;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int m = m0 + wm0 + i * 16 + lr;
+    if (m >= Mi) continue;
+#pragma unroll
+    for (int j = 0; j < FQ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + wq0 + j * 16 + 4 * lk + r;
+        if (q >= Qi) continue;
+        lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[i][j][r]);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3: K-major LDS (each lane reads its 8 consecutive k with one 16-byte
+// LDS load), operands split into hi/lo planes when the chunk is stored.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;                 // round to nearest even
+  lo = (__bf16)(x - (float)hi);   // exact difference in FP32, rounded to nearest even
+}
+
+template <typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int WGM, int WGQ>
+__global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs g) {
+  constexpr int NT = 64 * WGM * WGQ;
+  constexpr int KC = 32;                   // one MFMA K step per chunk
+  constexpr int LDK = KC + 8;              // padded K-major row (bf16 elements)
+  constexpr unsigned SA = sizeof(TA), SB = sizeof(TB);
+  constexpr int WM = TM / WGM, WQ = TQ / WGQ;
+  constexpr int FM = WM / 16, FQ = WQ / 16;
+  constexpr int AG = TM * KC / 8 / NT, BG = TQ * KC / 8 / NT;   // 8-element groups per thread
+  static_assert(AG * NT * 8 == TM * KC && BG * NT * 8 == TQ * KC, "tile / thread mismatch");
+  static_assert(FM >= 1 && FQ >= 1, "bad tile");
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][TM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][TM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][TQ * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][TQ * LDK];
+
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  const long T_ = xcd_remap((long)blockIdx.x, nt);
+  const long tq = T_ % g.tiles_q, rest = T_ / g.tiles_q;
+  const long tm = rest % g.tiles_m, b = rest / g.tiles_m;
+  const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
+  const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
+  const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
+  const TA* A = static_cast<const TA*>(g.A) + b * g.sA;
+  const unsigned abytes = (unsigned)(g.lda * g.K * SA);
+  const unsigned bbytes = BK ? (unsigned)(g.bq * g.Q * SB) : (unsigned)(g.bk * g.K * SB);
+  const __amdgpu_buffer_rsrc_t ra_src = make_rsrc(A, abytes);
+  const __amdgpu_buffer_rsrc_t rb_src = make_rsrc(static_cast<const TB*>(g.B), bbytes);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave % WGM) * WM, wq0 = (wave / WGM) * WQ;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // group p of this thread: A covers (m, 8 kg .. 8 kg + 7) with m fastest over threads;
+  // B likewise with q fastest, or (BK) 8 consecutive k of one column with kg fastest.
+  unsigned va[AG], vb[BG];
+#pragma unroll
+  for (int p = 0; p < AG; ++p) {
+    const int gi = tid + NT * p, m = gi % TM, kg = gi / TM;
+    va[p] = (m0 + m < Mi) ? ((unsigned)(m0 + m) + lda * (unsigned)(8 * kg)) * SA : abytes;
+  }
+#pragma unroll
+  for (int p = 0; p < BG; ++p) {
+    const int gi = tid + NT * p;
+    if (BK) {
+      const int kg = gi % (KC / 8), q = gi / (KC / 8);
+      vb[p] = ((unsigned)(8 * kg) + bq * (unsigned)(q0 + q)) * SB;
+    } else {
+      const int q = gi % TQ, kg = gi / TQ;
+      vb[p] = (q0 + q < Qi) ? ((unsigned)(q0 + q) + bk * (unsigned)(8 * kg)) * SB : bbytes;
+    }
+  }
+  v4f acc[FM][FQ];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FQ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  auto gload = [&](TA (&ra)[AG][8], TB (&rb)[BG][8], int k0) {
+#pragma unroll
+    for (int p = 0; p < AG; ++p)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[p][e] = buffer_ld_s<TA>(ra_src, va[p], lda * (unsigned)(k0 + e) * SA);
+#pragma unroll
+    for (int p = 0; p < BG; ++p) {
+      if constexpr (BK) {
+        const int kg = (tid + NT * p) % (KC / 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          rb[p][e] = buffer_ld_s<TB>(rb_src, (k0 + 8 * kg + e < Ki) ? vb[p] + (unsigned)e * SB : bbytes,
+                                     (unsigned)k0 * SB);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rb[p][e] = buffer_ld_s<TB>(rb_src, vb[p], bk * (unsigned)(k0 + e) * SB);
+      }
+    }
+  };
+  auto sstore = [&](const TA (&ra)[AG][8], const TB (&rb)[BG][8], int buf) {
+#pragma unroll
+    for (int p = 0; p < AG; ++p) {
+      const int gi = tid + NT * p, m = gi % TM, kg = gi / TM;
+      v8bf hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 h, l;
+        split_bf16((float)ra[p][e], h, l);
+        hi[e] = h;
+        lo[e] = l;
+      }
+      *reinterpret_cast<v8bf*>(&Ah[buf][m * LDK + 8 * kg]) = hi;
+      *reinterpret_cast<v8bf*>(&Al[buf][m * LDK + 8 * kg]) = lo;
+    }
+#pragma unroll
+    for (int p = 0; p < BG; ++p) {
+      const int gi = tid + NT * p;
+      const int q = BK ? gi / (KC / 8) : gi % TQ;
+      const int kg = BK ? gi % (KC / 8) : gi / TQ;
+      v8bf hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 h, l;
+        split_bf16((float)rb[p][e], h, l);
+        hi[e] = h;
+        lo[e] = l;
+      }
+      *reinterpret_cast<v8bf*>(&Bh[buf][q * LDK + 8 * kg]) = hi;
+      *reinterpret_cast<v8bf*>(&Bl[buf][q * LDK + 8 * kg]) = lo;
+    }
+  };
+  auto compute = [&](int cur) {
+    v8bf ah[FM], al[FM], bh[FQ], bl[FQ];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[cur][(wm0 + i * 16 + lr) * LDK + 8 * lk]);
+      al[i] = *reinterpret_cast<const v8bf*>(&Al[cur][(wm0 + i * 16 + lr) * LDK + 8 * lk]);
+    }
+#pragma unroll
+    for (int j = 0; j < FQ; ++j) {
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[cur][(wq0 + j * 16 + lr) * LDK + 8 * lk]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[cur][(wq0 + j * 16 + lr) * LDK + 8 * lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FQ; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah[i], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al[i], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah[i], acc[i][j], 0, 0, 0);
+      }
+  };
+  const int nk = (Ki + KC - 1) / KC;
+  TA ra0[AG][8], ra1[AG][8];
+  TB rb0[BG][8], rb1[BG][8];
+  gload(ra0, rb0, 0);
+  gload(ra1, rb1, KC);
+  sstore(ra0, rb0, 0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 2 < nk; kc += 2) {
+    gload(ra0, rb0, (kc + 2) * KC);
+    compute(0);
+    sstore(ra1, rb1, 1);
+    __syncthreads();
+    gload(ra1, rb1, (kc + 3) * KC);
+    compute(1);
+    sstore(ra0, rb0, 0);
+    __syncthreads();
+  }
+  compute(0);
+  if (kc + 1 < nk) {
+    sstore(ra1, rb1, 1);
+    __syncthreads();
+    compute(1);
+  }
+  const long cbase = b * g.sC;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int m = m0 + wm0 + i * 16 + lr;
+    if (m >= Mi) continue;
+#pragma unroll
+    for (int j = 0; j < FQ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + wq0 + j * 16 + 4 * lk + r;
+        if (q >= Qi) continue;
+        lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[i][j][r]);
+      }
+  }
+}
+
+template <int PREC, typename TA, typename TB, bool OUT32, bool BK>
+int launch_lp_typed(GemmArgs& g, hipStream_t s) {
+  // FP32: 128x64 on 8 waves (as FP64); BF16X3: 64x64 on 4 waves (the hi/lo split
+  // needs the registers of two prefetched chunks of 8-element groups)
+  constexpr int TM = PREC == EXPINT_PREC_FP32 ? 128 : 64, TQ = 64;
+  g.tiles_m = (g.M + TM - 1) / TM;
+  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  if (nt <= 0) return EXPINT_OK;
+  if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
+  if constexpr (PREC == EXPINT_PREC_FP32)
+    hipLaunchKernelGGL((k_mode_product_f32<TA, TB, OUT32, BK, TM, TQ, 16, 4, 2>), dim3((unsigned)nt), dim3(512), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_mode_product_bf16x3<TA, TB, OUT32, BK, TM, TQ, 2, 2>), dim3((unsigned)nt), dim3(256), 0, s, g);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
+  return EXPINT_OK;
+}
+
+// V (FP64 or FP32) and M (FP64) in; out0 FP32 (plain store) or the FP64 epilogue.
+template <int PREC, bool OUT32>
+int launch_lp_prec(bool v32, GemmArgs& g, bool mode1, hipStream_t s) {
+  if (mode1)  // Aop = M (FP64), Bop = V
+    return v32 ? launch_lp_typed<PREC, double, float, OUT32, true>(g, s)
+               : launch_lp_typed<PREC, double, double, OUT32, true>(g, s);
+  // Aop = V slab, Bop = M^T (FP64)
+  return v32 ? launch_lp_typed<PREC, float, double, OUT32, false>(g, s)
+             : launch_lp_typed<PREC, double, double, OUT32, false>(g, s);
+}
+
+}  // namespace
+
+int launch_mode_product_lp(int precision, bool v32, bool out32, long s, int n, long r, const void* M,
+                           const void* V, const Epilogue& epi, void* stream) {
+  if (s <= 0 || n <= 0 || r <= 0) return EXPINT_OK;
+  const long bytes = s * (long)n * r * 8;
+  if (bytes >= (1L << 31))
+    return set_error(EXPINT_ENOTSUP, "mode product: tensors of %ld bytes exceed the 2 GiB limit", bytes);
+  if (out32 && (epi.op != EPI_AXPBY || epi.alpha != 1.0 || epi.beta != 0.0))
+    return set_error(EXPINT_EINVAL, "reduced-precision intermediate modes only store plainly");
+  GemmArgs g;
+  g.epi = epi;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool mode1 = s == 1;
+  if (mode1) {
+    g.A = M; g.lda = n; g.B = V; g.bk = 1; g.bq = n;
+    g.M = n; g.Q = r; g.K = n; g.sA = 0; g.sC = 0; g.ldc = n; g.batches = 1;
+  } else {
+    g.A = V; g.lda = s; g.B = M; g.bk = n; g.bq = 1;
+    g.M = s; g.Q = n; g.K = n; g.sA = s * (long)n; g.sC = s * (long)n; g.ldc = s; g.batches = r;
+  }
+  if (precision == EXPINT_PREC_FP32)
+    return out32 ? launch_lp_prec<EXPINT_PREC_FP32, true>(v32, g, mode1, st)
+                 : launch_lp_prec<EXPINT_PREC_FP32, false>(v32, g, mode1, st);
+  if (precision == EXPINT_PREC_BF16X3)
+    return out32 ? launch_lp_prec<EXPINT_PREC_BF16X3, true>(v32, g, mode1, st)
+                 : launch_lp_prec<EXPINT_PREC_BF16X3, false>(v32, g, mode1, st);
+  return set_error(EXPINT_ENOTSUP, "unknown contraction precision %d", precision);
+}
+
+}  // namespace expint
