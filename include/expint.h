@@ -107,7 +107,10 @@ int phi_setup_z(int n, const double* A, int lda, double tau, int ell_max,
  *   W          device output tensor
  *   alpha,beta real scalars; beta == 0 means W is not read
  *   dtype      EXPINT_F64 or EXPINT_C128
- *   precision  EXPINT_PREC_FP64 (others: ENOTSUP for now)
+ *   precision  EXPINT_PREC_FP64, or (real data only) EXPINT_PREC_FP32 /
+ *              EXPINT_PREC_BF16X3: operands rounded to FP32 or split into two
+ *              bf16 parts, FP32 accumulation, FP32 intermediates between
+ *              modes, FP64 result
  *   ws         device workspace of at least tucker_workspace_size() bytes
  *              (may be NULL when that size is 0)
  *   stream     hipStream_t
@@ -136,7 +139,9 @@ typedef struct expint_problem {
   int nonlin;            /* EXPINT_G_* */
   double g_param;        /* kappa of EXPINT_G_CUBIC_NLS, unused otherwise */
   int dtype;             /* EXPINT_F64 or EXPINT_C128 */
-  int precision;         /* EXPINT_PREC_FP64 */
+  int precision;         /* contraction precision of the Tucker operators (EXPINT_PREC_*;
+                            reduced precision for real data only); K u, g and the
+                            stage combination stay FP64 */
 } expint_problem;
 
 /*
@@ -180,6 +185,53 @@ int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
 /* expint_plan_destroy -- frees the plan's device memory and graph (NULL is a no-op).
  * The caller must make sure no enqueued work still uses the plan. */
 void expint_plan_destroy(expint_plan* plan);
+
+/* ------------------------------------------------------------------------ */
+/* batched Riccati differential equations                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct expint_batch_plan expint_batch_plan;
+
+/*
+ * expint_riccati_plan_create -- `count` independent instances of
+ *     U' = A1 U + U A2^T + C + U B U,   U n1 x n2, B n2 x n1, C n1 x n2
+ * (section 1, eq. Riccati; Kronecker form eq. ODE2d), each integrated with
+ * ETD2RK phisplit (section 3.2; for d = 2 the phi_2 stage carries the split
+ * factor 2).  phi_1 and phi_2 of tau A1 and tau A2 are built once on the host
+ * in FP64.  A step is ten GEMM phases; each phase is one persistent launch
+ * over all instances, most expensive instances first.
+ *   count   >= 1
+ *   n1, n2  host arrays of count sizes, 1..4096
+ *   A1, A2  host arrays of count host pointers, column-major n1 x n1 / n2 x n2 float64
+ *   B, C    device float64, packed: instance i's B (column-major n2 x n1) and C
+ *           (column-major n1 x n2) both start at element offset
+ *           off_i = sum_{j<i} n1[j] n2[j].  They must stay valid while the plan is used.
+ *   tau     step size
+ * The state is one device array of sum n1 n2 float64 with instance i (column-major
+ * n1 x n2) at off_i.  Errors: EINVAL, ENOTSUP, ENOMEM, EHIP.
+ */
+int expint_riccati_plan_create(expint_batch_plan** plan, int count, const int* n1, const int* n2,
+                               const double* const* A1, const double* const* A2,
+                               const double* B, const double* C, double tau);
+
+/* expint_batch_state_size -- elements of the packed state (sum n1 n2). */
+int expint_batch_state_size(const expint_batch_plan* plan, size_t* elements);
+
+/* expint_batch_workspace_size -- device workspace bytes of expint_batch_step/run. */
+int expint_batch_workspace_size(const expint_batch_plan* plan, size_t* bytes);
+
+/*
+ * expint_batch_step / expint_batch_run -- one step / nsteps steps of every
+ * instance, U (device, packed state) updated in place.  The first call with a
+ * given (U, ws) pair builds and uploads the GEMM descriptors synchronously;
+ * later calls with the same pair only enqueue.  use_graph != 0 replays one
+ * captured step (needs a non-default stream).
+ */
+int expint_batch_step(expint_batch_plan* plan, double* U, void* ws, void* stream);
+int expint_batch_run(expint_batch_plan* plan, double* U, int nsteps, int use_graph, void* ws, void* stream);
+
+/* expint_batch_plan_destroy -- frees the plan (NULL is a no-op). */
+void expint_batch_plan_destroy(expint_batch_plan* plan);
 
 /* expint_last_error -- thread-local message of the last failing call ("" if none). */
 const char* expint_last_error(void);

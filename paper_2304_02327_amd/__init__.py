@@ -17,6 +17,7 @@ from ._binding import (  # noqa: F401
     SCHEMES,
     ExpintError,
     Plan,
+    RiccatiBatch,
     matrix_to_device,
     phi_setup,
     tensor_from_device,

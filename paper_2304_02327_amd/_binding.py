@@ -58,6 +58,15 @@ def _load():
     lib.expint_run.argtypes = [c_void_p, c_void_p, c_double, c_int, c_int, c_void_p, c_void_p]
     lib.expint_plan_destroy.argtypes = [c_void_p]
     lib.expint_plan_destroy.restype = None
+    lib.expint_riccati_plan_create.argtypes = [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_int),
+                                               ctypes.POINTER(c_int), ctypes.POINTER(dp), ctypes.POINTER(dp),
+                                               c_void_p, c_void_p, c_double]
+    lib.expint_batch_state_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
+    lib.expint_batch_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
+    lib.expint_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.expint_batch_run.argtypes = [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]
+    lib.expint_batch_plan_destroy.argtypes = [c_void_p]
+    lib.expint_batch_plan_destroy.restype = None
     lib.expint_last_error.restype = ctypes.c_char_p
     lib.expint_version.restype = ctypes.c_char_p
     return lib
@@ -69,6 +78,8 @@ EXPORTED_SYMBOLS = (
     "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_destroy", "expint_last_error", "expint_version",
+    "expint_riccati_plan_create", "expint_batch_state_size", "expint_batch_workspace_size",
+    "expint_batch_step", "expint_batch_run", "expint_batch_plan_destroy",
 )
 
 
@@ -284,3 +295,92 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# batched Riccati instances
+# ---------------------------------------------------------------------------
+
+def _pack_colmajor(mats):
+    """Concatenate matrices in column-major order (natural-index numpy inputs)."""
+    return np.concatenate([np.asarray(m, dtype=np.float64).ravel(order="F") for m in mats])
+
+
+def _unpack_colmajor(flat, shapes):
+    out, o = [], 0
+    for r, c in shapes:
+        out.append(flat[o:o + r * c].reshape((r, c), order="F").copy())
+        o += r * c
+    return out
+
+
+class RiccatiBatch:
+    """ETD2RK phisplit for many instances of U' = A1 U + U A2^T + C + U B U.
+
+    ``instances`` hold natural-index host matrices (A1, A2, B, C, U0).  B and C
+    are uploaded once and owned by this object; the state is one packed device
+    array (instance i column-major at offset sum_{j<i} n1_j n2_j).
+    """
+
+    def __init__(self, instances, tau: float, device="cuda"):
+        import torch
+        self.n1 = [int(x.n1) for x in instances]
+        self.n2 = [int(x.n2) for x in instances]
+        self.count = len(instances)
+        self.device = torch.device(device)
+        self.B = torch.from_numpy(_pack_colmajor([x.B for x in instances])).to(self.device)
+        self.C = torch.from_numpy(_pack_colmajor([x.C for x in instances])).to(self.device)
+        hostA1 = [np.asfortranarray(x.A1, dtype=np.float64) for x in instances]
+        hostA2 = [np.asfortranarray(x.A2, dtype=np.float64) for x in instances]
+        a1 = (dp_type() * self.count)(*[m.ctypes.data_as(dp_type()) for m in hostA1])
+        a2 = (dp_type() * self.count)(*[m.ctypes.data_as(dp_type()) for m in hostA2])
+        n1 = (ctypes.c_int * self.count)(*self.n1)
+        n2 = (ctypes.c_int * self.count)(*self.n2)
+        self._handle = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(lib.expint_riccati_plan_create(ctypes.byref(self._handle), self.count, n1, n2, a1, a2,
+                                                  self.B.data_ptr(), self.C.data_ptr(), float(tau)))
+        size = ctypes.c_size_t(0)
+        _check(lib.expint_batch_workspace_size(self._handle, ctypes.byref(size)))
+        self.ws = torch.empty(max(size.value, 16), dtype=torch.uint8, device=self.device)
+        _check(lib.expint_batch_state_size(self._handle, ctypes.byref(size)))
+        self.state_size = size.value
+
+    def state_to_device(self, mats):
+        import torch
+        return torch.from_numpy(_pack_colmajor(mats)).to(self.device)
+
+    def state_from_device(self, U):
+        return _unpack_colmajor(U.detach().cpu().numpy(), list(zip(self.n1, self.n2)))
+
+    def _check_state(self, U):
+        import torch
+        _check_device_tensor(U, "U")
+        if U.dtype != torch.float64 or U.numel() != self.state_size:
+            raise ValueError(f"U must be a float64 device tensor of {self.state_size} elements")
+
+    def step(self, U, stream=None):
+        self._check_state(U)
+        _check(lib.expint_batch_step(self._handle, U.data_ptr(), self.ws.data_ptr(), _stream_handle(stream)))
+        return U
+
+    def run(self, U, nsteps: int, use_graph: bool = False, stream=None):
+        self._check_state(U)
+        _check(lib.expint_batch_run(self._handle, U.data_ptr(), int(nsteps), 1 if use_graph else 0,
+                                    self.ws.data_ptr(), _stream_handle(stream)))
+        return U
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            lib.expint_batch_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dp_type():
+    return ctypes.POINTER(ctypes.c_double)

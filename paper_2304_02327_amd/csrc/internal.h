@@ -13,6 +13,8 @@ int set_error(int code, const char* fmt, ...);
 
 int phi_setup_real(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
 int phi_setup_complex(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
+// keep this thread's phi_setup calls on one host thread (callers that already parallelise)
+void phi_setup_single_threaded(bool on);
 
 // ---------------------------------------------------------------------------
 // mu-mode product launcher
@@ -26,6 +28,7 @@ enum EpiOp : int {
   EPI_ETD2RK_1 = 2,     // u = in1[e]; u2 = u + Y; out0[e] = u2; out1[e] = tau (g(u2) - g(u))
   EPI_ETD2RK_2 = 3,     // out0[e] = in1[e] + c * Y
   EPI_LAWSON2B_2 = 4,   // out0[e] = Y + c * g(in1[e])           (c = tau / 2)
+  EPI_LINEAR = 5,       // out0[e] = alpha Y + beta in1[e] + c in2[e]   (in1 / in2 optional)
 };
 
 struct Epilogue {
@@ -34,6 +37,7 @@ struct Epilogue {
   double alpha = 1.0, beta = 0.0, tau = 0.0, c = 0.0, gparam = 0.0;
   void* out0 = nullptr;        // primary output (always written)
   const void* in1 = nullptr;   // secondary input
+  const void* in2 = nullptr;   // third input (EPI_LINEAR)
   void* out1 = nullptr;        // secondary output
 };
 
@@ -42,6 +46,18 @@ struct Epilogue {
 // epilogue decides what is stored.  dtype EXPINT_F64 or EXPINT_C128.
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
                         const Epilogue& epi, void* stream);
+
+// Grouped FP64 GEMMs in one persistent launch (batched instances).  A
+// descriptor describes C[m, q] = sum_k A[m + lda k] B[k bk + q bq] for
+// m < M, q < Q, k < K with output element m + ldc q and an epilogue;
+// bk == 1 (B contiguous along k) or bq == 1 (contiguous along q) selects the
+// kernel.  `start` (device, count + 1 entries) holds the tile prefix sums.
+size_t gemm_desc_size();
+int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
+                   long ldc, const Epilogue& epi);
+long gemm_desc_tiles(const void* desc);
+int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
+                        void* stream);
 
 // Reduced-precision contraction (EXPINT_PREC_FP32 / EXPINT_PREC_BF16X3) of a real
 // mu-mode product: V is FP32 when v32 (else FP64), M is FP64; with out32 the

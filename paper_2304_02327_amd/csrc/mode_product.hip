@@ -83,6 +83,13 @@ __device__ __forceinline__ void epilogue_store(const Epilogue& ep, long e, T y) 
     case EPI_LAWSON2B_2:
       out0[e] = add(y, scale(g_eval(ep.g, ld<T>(ep.in1, e), ep.gparam), ep.c));
       break;
+    case EPI_LINEAR: {
+      T v = scale(y, ep.alpha);
+      if (ep.in1) v = add(v, scale(ld<T>(ep.in1, e), ep.beta));
+      if (ep.in2) v = add(v, scale(ld<T>(ep.in2, e), ep.c));
+      out0[e] = v;
+      break;
+    }
     default:
       break;
   }
@@ -110,8 +117,11 @@ __device__ __forceinline__ cdouble buffer_ld<cdouble>(__amdgpu_buffer_rsrc_t r, 
   return __builtin_bit_cast(cdouble, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
 
+// One TM x TQ output tile (tile index T_ in [0, tiles_m tiles_q batches)) of the
+// GEMM described by g, computed by the whole workgroup.  Used by the single
+// launch below and by the persistent grouped launch.
 template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
-__global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   constexpr bool CPLX = std::is_same<T, cdouble>::value;
   constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
   constexpr int NT = 64 * WGM * WGQ;                // threads
@@ -127,8 +137,6 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
   __shared__ double As[2][NP][KC * LDA_S];
   __shared__ double Bs[2][NP][KC * LDB_S];
 
-  const long nt = g.tiles_m * g.tiles_q * g.batches;
-  const long T_ = xcd_remap((long)blockIdx.x, nt);
   const long tq = T_ % g.tiles_q;
   const long rest = T_ / g.tiles_q;
   const long tm = rest % g.tiles_m;
@@ -301,6 +309,34 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
 }
 
 template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+__global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ>(g, xcd_remap((long)blockIdx.x, nt));
+}
+
+// Persistent grouped GEMM: `count` independent GEMMs (one descriptor each,
+// tiles_m/tiles_q filled in, listed in decreasing cost) share one launch.
+// Tile t belongs to the descriptor i with start[i] <= t < start[i + 1]; each
+// workgroup walks t = blockIdx.x, blockIdx.x + gridDim.x, ... so the costly
+// tiles at the front are spread over every workgroup (longest first).
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+__global__ __launch_bounds__(64 * WGM * WGQ) void k_grouped_gemm(const GemmArgs* __restrict__ descs,
+                                                                 const long* __restrict__ start, int count) {
+  const long total = start[count];
+  for (long t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = count - 1;  // last i with start[i] <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const GemmArgs g = descs[lo];
+    __syncthreads();  // the previous tile's last LDS reads are done before this tile's stores
+    gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ>(g, t - start[lo]);
+  }
+}
+
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
 int launch_tile(GemmArgs& g, hipStream_t s) {
   g.tiles_m = (g.M + TM - 1) / TM;
   g.tiles_q = (g.Q + TQ - 1) / TQ;
@@ -359,6 +395,61 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
 }
 
 }  // namespace
+
+int grouped_tile_shape(int* tm, int* tq) {
+  *tm = 64;
+  *tq = 64;
+  return EXPINT_OK;
+}
+
+int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
+                        void* stream) {
+  if (count <= 0 || total_tiles <= 0) return EXPINT_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long grid = total_tiles < 2048 ? total_tiles : 2048;
+  const GemmArgs* d = static_cast<const GemmArgs*>(descs);
+  if (bk_contiguous)
+    hipLaunchKernelGGL((k_grouped_gemm<double, true, 64, 64, 32, 2, 4>), dim3((unsigned)grid), dim3(512), 0, st, d,
+                       start, count);
+  else
+    hipLaunchKernelGGL((k_grouped_gemm<double, false, 64, 64, 32, 2, 4>), dim3((unsigned)grid), dim3(512), 0, st, d,
+                       start, count);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return set_error(EXPINT_EHIP, "grouped GEMM launch failed: %s", hipGetErrorString(err));
+  return EXPINT_OK;
+}
+
+size_t gemm_desc_size() { return sizeof(GemmArgs); }
+
+int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
+                   long ldc, const Epilogue& epi) {
+  int tm, tq;
+  grouped_tile_shape(&tm, &tq);
+  GemmArgs g;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.bk = bk;
+  g.bq = bq;
+  g.M = M;
+  g.Q = Q;
+  g.K = K;
+  g.sA = 0;
+  g.sC = 0;
+  g.ldc = ldc;
+  g.batches = 1;
+  g.tiles_m = (M + tm - 1) / tm;
+  g.tiles_q = (Q + tq - 1) / tq;
+  g.epi = epi;
+  std::memcpy(out, &g, sizeof(g));
+  return EXPINT_OK;
+}
+
+long gemm_desc_tiles(const void* desc) {
+  GemmArgs g;
+  std::memcpy(&g, desc, sizeof(g));
+  return g.tiles_m * g.tiles_q * g.batches;
+}
 
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
                         const Epilogue& epi, void* stream) {

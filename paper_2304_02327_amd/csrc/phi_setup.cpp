@@ -23,6 +23,7 @@ namespace expint {
 namespace {
 
 using cplx = std::complex<double>;
+thread_local bool t_single_threaded = false;
 
 inline double absval(double x) { return std::fabs(x); }
 inline double absval(const cplx& x) { return std::abs(x); }
@@ -51,7 +52,7 @@ void matmul(int n, const T* A, const T* B, T* C) {
   };
   const double work = double(n) * n * n;
   unsigned nt = 1;
-  if (work > 2.0e6) {
+  if (work > 2.0e6 && !t_single_threaded) {
     nt = std::thread::hardware_concurrency();
     if (nt == 0) nt = 1;
     if (nt > 16) nt = 16;
@@ -148,6 +149,8 @@ int phi_setup_impl(int n, const T* A, int lda, double tau, int ell_max, T* out, 
 }
 
 }  // namespace
+
+void phi_setup_single_threaded(bool on) { t_single_threaded = on; }
 
 int phi_setup_real(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo) {
   return phi_setup_impl<double>(n, A, lda, tau, ell_max, out, ldo);

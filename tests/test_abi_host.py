@@ -117,7 +117,8 @@ def test_tucker_workspace_size_and_validation():
     assert B.lib.tucker_apply(0, n, ptrs, None, None, 1.0, 0.0, 0, 0, None, 0, None) == B.EINVAL
     assert B.lib.tucker_apply(2, n, ptrs, None, None, 1.0, 0.0, 0, 0, None, 0, None) == B.EINVAL
     assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 7, 0, None, 0, None) == B.EINVAL
-    assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 0, 5, None, 0, None) == B.ENOTSUP
+    assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 0, 5, None, 0, None) == B.EINVAL  # unknown precision
+    assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 1, 1, None, 0, None) == B.ENOTSUP  # complex + FP32
     # every matrix NULL
     assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 0, 0, None, 0, None) == B.EINVAL
 
@@ -142,8 +143,12 @@ def test_plan_create_rejects_bad_problems():
     prob.nonlin = 3  # cubic NLS on real data
     assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
     prob.nonlin = 2
-    prob.precision = 2
-    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
+    prob.precision = 7
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.EINVAL
+    prob.precision = 1
+    prob.dtype = 1
+    prob.nonlin = 3
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP  # complex + FP32
     assert B.lib.expint_step(None, None, 0.0, None, None) == B.EINVAL
 
 
@@ -158,3 +163,20 @@ def test_single_hip_runtime_in_process():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True)
     assert out.stdout.strip() == "1", out.stdout + out.stderr
+
+
+def test_riccati_plan_rejects_bad_arguments():
+    h = ctypes.c_void_p(None)
+    n = (ctypes.c_int * 2)(4, 0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    A = np.eye(4)
+    mats = (dp * 2)(A.ctypes.data_as(dp), A.ctypes.data_as(dp))
+    assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 0, n, n, mats, mats, 16, 16, 0.1) == B.EINVAL
+    assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, n, n, mats, mats, 16, 16, 0.1) == B.EINVAL
+    n2 = (ctypes.c_int * 2)(4, 4)
+    assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, n2, n2, mats, mats, None, 16, 0.1) == B.EINVAL
+    assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, n2, n2, mats, mats, 16, 16, float("inf")) == B.EINVAL
+    big = (ctypes.c_int * 2)(5000, 4)
+    assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, big, n2, mats, mats, 16, 16, 0.1) == B.ENOTSUP
+    assert h.value is None
+    assert B.lib.expint_batch_step(None, None, None, None) == B.EINVAL

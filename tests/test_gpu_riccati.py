@@ -1,0 +1,100 @@
+"""Batched Riccati instances (persistent grouped GEMM launches) against the oracle.
+
+Each instance U' = A1 U + U A2^T + C + U B U is stepped with ETD2RK phisplit by
+the library (ten grouped GEMM phases per step) and, independently, by the
+oracle's tensor-form ETD2RK with g = C + U B U.  Bar: relative max-norm error
+<= 1e-12 per instance (FP64 throughout).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2304_02327_amd as px
+import workloads as W
+from oracle import nonlinear, schemes
+from oracle.norms import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _with_random_start(insts, seed):
+    rng = np.random.default_rng(seed)
+    for x in insts:
+        x.U0 = 0.3 * rng.standard_normal((x.n1, x.n2))
+    return insts
+
+
+def _oracle(inst, tau, steps):
+    g = nonlinear.make_g("riccati", {"B": inst.B, "C": inst.C})
+    return schemes.Integrator([inst.A1, inst.A2], tau, "etd2rk", g).run(inst.U0, 0.0, steps)
+
+
+def _gpu(insts, tau, steps, use_graph=False):
+    batch = px.RiccatiBatch(insts, tau)
+    U = batch.state_to_device([x.U0 for x in insts])
+    if use_graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch.run(U, steps, use_graph=True, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+    else:
+        batch.run(U, steps)
+    torch.cuda.synchronize()
+    out = batch.state_from_device(U)
+    batch.close()
+    return out
+
+
+def test_small_uneven_batch():
+    insts = _with_random_start(W.riccati_batch(count=7, nmin=5, nmax=70, seed=31), 32)
+    tau = 1e-3
+    got = _gpu(insts, tau, 6)
+    for x, u in zip(insts, got):
+        assert rel_inf(u, _oracle(x, tau, 6)) <= TOL, (x.n1, x.n2)
+
+
+def test_tile_straddling_and_both_associations():
+    """Sizes around the 64-wide tiles, n1 < n2 (T = U B) and n1 > n2 (T = B U), size 1."""
+    base = W.riccati_batch(count=6, nmin=5, nmax=9, seed=33)
+    sizes = [(63, 64), (65, 64), (130, 33), (33, 130), (1, 7), (7, 1)]
+    rng = np.random.default_rng(34)
+    insts = []
+    for (n1, n2), b in zip(sizes, base):
+        b.n1, b.n2 = n1, n2
+        b.A1 = W.dirichlet_d2(n1, 1.0 / (n1 + 1)) + 0.1 * rng.standard_normal((n1, n1))
+        b.A2 = W.dirichlet_d2(n2, 1.0 / (n2 + 1)) + 0.1 * rng.standard_normal((n2, n2))
+        b.B = 0.1 * rng.standard_normal((n2, n1))
+        b.C = 0.1 * rng.standard_normal((n1, n2))
+        insts.append(b)
+    insts = _with_random_start(insts, 35)
+    tau = 2e-3
+    got = _gpu(insts, tau, 5)
+    for x, u in zip(insts, got):
+        assert rel_inf(u, _oracle(x, tau, 5)) <= TOL, (x.n1, x.n2)
+
+
+def test_graph_replay_equals_direct():
+    insts = _with_random_start(W.riccati_batch(count=5, nmin=20, nmax=90, seed=36), 37)
+    a = _gpu(insts, 1e-3, 4, use_graph=True)
+    b = _gpu(insts, 1e-3, 4, use_graph=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_full_batch_sampled_instances():
+    """The full 64-instance configuration (n1, n2 in 32..512, U0 = 0) in graph mode;
+    the oracle checks four sampled instances, the largest among them."""
+    insts = W.riccati_batch()
+    tau = 1e-3
+    steps = 3
+    got = _gpu(insts, tau, steps, use_graph=True)
+    cost = [x.n1 * x.n2 * (x.n1 + x.n2) for x in insts]
+    sample = sorted(set([int(np.argmax(cost)), int(np.argmin(cost)), 17, 40]))
+    for i in sample:
+        ref = _oracle(insts[i], tau, steps)
+        assert rel_inf(got[i], ref) <= TOL, (i, insts[i].n1, insts[i].n2)
+    assert all(np.isfinite(u).all() for u in got)
