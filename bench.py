@@ -92,6 +92,93 @@ def tucker_flops_per_step(p) -> float:
     return tuckers * per_tucker
 
 
+def riccati_flops_per_step(insts) -> float:
+    """Algorithmic flops of one ETD2RK step of every instance: T and G (twice each,
+    2 n1 n2 min(n1, n2) apiece), K u (2 n1^2 n2 + 2 n1 n2^2) and two Tucker operators
+    (the same again each)."""
+    tot = 0.0
+    for x in insts:
+        n1, n2 = x.n1, x.n2
+        tot += n1 * n2 * (8 * min(n1, n2) + 6 * n1 + 6 * n2)
+    return tot
+
+
+def bench_riccati(args):
+    """64 Riccati-type instances, n1, n2 ~ U{32..512}, ETD2RK phisplit, FP64."""
+    import numpy as np
+    import torch
+    import paper_2304_02327_amd as px
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    insts = W.riccati_batch()
+    tau = 1e-3
+    t = time.perf_counter()
+    batch = px.RiccatiBatch(insts, tau, device=dev)
+    setup_s = time.perf_counter() - t
+    U0 = batch.state_to_device([x.U0 for x in insts])
+    U = U0.clone()
+    N = batch.state_size
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        batch.run(U, args.warmup, use_graph=True, stream=stream)
+    stream.synchronize()
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    with torch.cuda.stream(stream):
+        batch.run(U, args.steps, use_graph=True, stream=stream)
+    ev1.record(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    flops = riccati_flops_per_step(insts)
+    tf = flops * args.steps / (gpu_ms / 1e3) / 1e12
+    result = {
+        "metric": METRIC, "value": N * args.steps / (gpu_ms / 1e3), "unit": "DOF-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": gpu_ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "64 Riccati-type instances, n1,n2 ~ U{32..512}, ETD2RK phisplit, FP64, tau=1e-3",
+                   "dof": N, "graph": True, "launches_per_step": 10},
+        "wall_s_timed_region": wall, "phi_setup_s": setup_s,
+        "roofline": {"kernel": "k_grouped_gemm (10 persistent FP64 MFMA launches per step)", "bound": "mfma",
+                     "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "flops_per_step": flops, "avg_launch_us": round(gpu_ms * 1e3 / args.steps / 10, 3)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import nonlinear, schemes
+        from oracle.norms import rel_inf
+        sample = list(range(0, 64, 8))  # 8 of the 64 instances
+        k = 3
+        t = time.perf_counter()
+        integs = []
+        for i in sample:
+            x = insts[i]
+            g = nonlinear.make_g("riccati", {"B": x.B, "C": x.C})
+            integs.append(schemes.Integrator([x.A1, x.A2], tau, "etd2rk", g))
+        osetup = time.perf_counter() - t
+        t = time.perf_counter()
+        outs = [integ.run(insts[i].U0, 0.0, k) for integ, i in zip(integs, sample)]
+        secs = time.perf_counter() - t
+        Ug = U0.clone()
+        batch.run(Ug, k)
+        torch.cuda.synchronize()
+        got = batch.state_from_device(Ug)
+        err = max(rel_inf(got[i], o) for i, o in zip(sample, outs))
+        dof = sum(insts[i].n1 * insts[i].n2 for i in sample)
+        result["cpu_baseline"] = {"value": dof * k / secs, "unit": "DOF-steps/s", "cores": os.cpu_count(),
+                                  "kind": "oracle", "sample": f"{k} steps of instances {sample} (oracle phi setup "
+                                  f"{osetup:.1f} s excluded)", "seconds": round(secs, 3),
+                                  "gpu_vs_oracle_rel_inf": err}
+    batch.close()
+    print(json.dumps(result))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +200,9 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(sharding is described in the design notes only).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "riccati64":
+        bench_riccati(args)
+        return
 
     import numpy as np
     import torch
