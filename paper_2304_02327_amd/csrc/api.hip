@@ -77,7 +77,7 @@ int tucker_chain(int dtype, int precision, int d, const int* n, const void* cons
     mode_view(d, n, mu, &s, &r);
     if (mu == lastmu) {
       if (lp)
-        TRY(launch_mode_product_lp(precision, src32, false, s, n[mu], r, M[mu], src, last, stream));
+        TRY(launch_mode_product_lp(precision, dtype == EXPINT_C128, src32, false, s, n[mu], r, M[mu], src, last, stream));
       else
         TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, last, stream));
     } else {
@@ -87,7 +87,7 @@ int tucker_chain(int dtype, int precision, int d, const int* n, const void* cons
       e.beta = 0.0;
       e.out0 = bufs[which];
       if (lp)
-        TRY(launch_mode_product_lp(precision, src32, true, s, n[mu], r, M[mu], src, e, stream));
+        TRY(launch_mode_product_lp(precision, dtype == EXPINT_C128, src32, true, s, n[mu], r, M[mu], src, e, stream));
       else
         TRY(launch_mode_product(dtype, s, n[mu], r, M[mu], src, e, stream));
       src = bufs[which];
@@ -168,8 +168,8 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   TRY(validate_shape(d, n, &N));
   if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
   if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "tucker_apply: unknown precision %d", precision);
-  if (precision != EXPINT_PREC_FP64 && dtype != EXPINT_F64)
-    return set_error(EXPINT_ENOTSUP, "tucker_apply: reduced precision is implemented for real data only");
+  if (precision == EXPINT_PREC_BF16X3 && dtype != EXPINT_F64)
+    return set_error(EXPINT_ENOTSUP, "tucker_apply: complex data supports FP64 or FP32 (complex64) contraction");
   if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
   if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
   if (!aligned16(V) || !aligned16(W)) return set_error(EXPINT_EINVAL, "tucker_apply: V and W must be 16-byte aligned");
@@ -409,8 +409,8 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)
     return set_error(EXPINT_EINVAL, "unknown dtype %d", prob->dtype);
   if (!valid_precision(prob->precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", prob->precision);
-  if (prob->precision != EXPINT_PREC_FP64 && prob->dtype != EXPINT_F64)
-    return set_error(EXPINT_ENOTSUP, "reduced contraction precision is implemented for real data only");
+  if (prob->precision == EXPINT_PREC_BF16X3 && prob->dtype != EXPINT_F64)
+    return set_error(EXPINT_ENOTSUP, "complex data supports FP64 or FP32 (complex64) contraction");
   if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
   const bool cplx = prob->dtype == EXPINT_C128;
   if (cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_CUBIC_NLS)

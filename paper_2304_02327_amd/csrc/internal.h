@@ -59,10 +59,11 @@ long gemm_desc_tiles(const void* desc);
 int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
                         void* stream);
 
-// Reduced-precision contraction (EXPINT_PREC_FP32 / EXPINT_PREC_BF16X3) of a real
-// mu-mode product: V is FP32 when v32 (else FP64), M is FP64; with out32 the
-// result is stored plainly as FP32 into epi.out0, else it runs the FP64 epilogue.
-int launch_mode_product_lp(int precision, bool v32, bool out32, long s, int n, long r, const void* M,
+// Reduced-precision contraction (EXPINT_PREC_FP32 / EXPINT_PREC_BF16X3; complex
+// data FP32 only) of a mu-mode product: V is FP32 (complex64) when v32, else
+// FP64 (complex128), M is FP64 / complex128; with out32 the result is stored
+// plainly in single precision into epi.out0, else it runs the FP64 epilogue.
+int launch_mode_product_lp(int precision, bool cplx, bool v32, bool out32, long s, int n, long r, const void* M,
                            const void* V, const Epilogue& epi, void* stream);
 
 // ---------------------------------------------------------------------------

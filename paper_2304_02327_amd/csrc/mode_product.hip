@@ -518,6 +518,20 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+struct __attribute__((aligned(8))) cfloat {
+  float re, im;
+};
+template <typename T> struct is_cplx : std::false_type {};
+template <> struct is_cplx<cdouble> : std::true_type {};
+template <> struct is_cplx<cfloat> : std::true_type {};
+__device__ __forceinline__ float re_f(double x) { return (float)x; }
+__device__ __forceinline__ float re_f(float x) { return x; }
+__device__ __forceinline__ float re_f(cdouble x) { return (float)x.re; }
+__device__ __forceinline__ float re_f(cfloat x) { return x.re; }
+__device__ __forceinline__ float im_f(cdouble x) { return (float)x.im; }
+__device__ __forceinline__ float im_f(cfloat x) { return x.im; }
+template <typename T> __device__ __forceinline__ float im_f(T) { return 0.f; }
+
 template <typename T>
 __device__ __forceinline__ T buffer_ld_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
 template <>
@@ -527,6 +541,14 @@ __device__ __forceinline__ double buffer_ld_s<double>(__amdgpu_buffer_rsrc_t r, 
 template <>
 __device__ __forceinline__ float buffer_ld_s<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ cdouble buffer_ld_s<cdouble>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(cdouble, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ cfloat buffer_ld_s<cfloat>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(cfloat, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
 struct GemmArgsLP {
@@ -540,12 +562,22 @@ __device__ __forceinline__ void lp_store(const Epilogue& ep, long e, float y) {
   else
     epilogue_store<double>(ep, e, (double)y);
 }
+template <bool OUT32>
+__device__ __forceinline__ void lp_store_c(const Epilogue& ep, long e, float yr, float yi) {
+  if constexpr (OUT32)
+    static_cast<cfloat*>(ep.out0)[e] = cfloat{yr, yi};
+  else
+    epilogue_store<cdouble>(ep, e, cdouble{(double)yr, (double)yi});
+}
 
 // ---------------------------------------------------------------------------
 // FP32: structure of the FP64 kernel with an FP32 LDS and f32 MFMA
 // ---------------------------------------------------------------------------
 template <typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
 __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g) {
+  constexpr bool CPLX = is_cplx<TA>::value;
+  static_assert(CPLX == is_cplx<TB>::value, "operands must both be real or both complex");
+  constexpr int NP = CPLX ? 2 : 1;
   constexpr int NT = 64 * WGM * WGQ;
   constexpr unsigned SA = sizeof(TA), SB = sizeof(TB);
   constexpr int LDA_S = TM, LDB_S = BK ? TQ + 1 : TQ;
@@ -554,8 +586,8 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
   constexpr int AL = TM * KC / NT, BL = TQ * KC / NT;
   static_assert(AL * NT == TM * KC && BL * NT == TQ * KC, "tile / thread mismatch");
   static_assert(FM >= 1 && FQ >= 1 && KC % 4 == 0, "bad tile");
-  __shared__ float As[2][KC * LDA_S];
-  __shared__ float Bs[2][KC * LDB_S];
+  __shared__ float As[2][NP][KC * LDA_S];
+  __shared__ float Bs[2][NP][KC * LDB_S];
 
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   const long T_ = xcd_remap((long)blockIdx.x, nt);
@@ -588,11 +620,13 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
     else
       vb[p] = (q0 + q < Qi) ? ((unsigned)(q0 + q) + bk * (unsigned)k) * SB : bbytes;
   }
-  v4f acc[FM][FQ];
+  v4f acc[NP][FM][FQ];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int j = 0; j < FQ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FQ; ++j) acc[p][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
   auto gload = [&](TA (&ra)[AL], TB (&rb)[BL], int k0) {
     const unsigned sa = lda * (unsigned)k0 * SA;
@@ -614,27 +648,41 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
 #pragma unroll
     for (int p = 0; p < AL; ++p) {
       const int idx = tid + NT * p, m = idx % TM, k = idx / TM;
-      As[buf][k * LDA_S + m] = (float)ra[p];
+      As[buf][0][k * LDA_S + m] = re_f(ra[p]);
+      if constexpr (CPLX) As[buf][1][k * LDA_S + m] = im_f(ra[p]);
     }
 #pragma unroll
     for (int p = 0; p < BL; ++p) {
       const int idx = tid + NT * p;
       const int q = BK ? idx / KC : idx % TQ, k = BK ? idx % KC : idx / TQ;
-      Bs[buf][k * LDB_S + q] = (float)rb[p];
+      Bs[buf][0][k * LDB_S + q] = re_f(rb[p]);
+      if constexpr (CPLX) Bs[buf][1][k * LDB_S + q] = im_f(rb[p]);
     }
   };
   auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      float af[FM], bf[FQ];
+      float af[NP][FM], bf[NP][FQ];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[cur][(kk + lk) * LDA_S + wm0 + i * 16 + lr];
+      for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int j = 0; j < FQ; ++j) bf[j] = Bs[cur][(kk + lk) * LDB_S + wq0 + j * 16 + lr];
+        for (int i = 0; i < FM; ++i) af[p][i] = As[cur][p][(kk + lk) * LDA_S + wm0 + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < FQ; ++j) bf[p][j] = Bs[cur][p][(kk + lk) * LDB_S + wq0 + j * 16 + lr];
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FQ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[j], af[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FQ; ++j) {
+          if constexpr (CPLX) {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[0][j], af[0][i], acc[0][i][j], 0, 0, 0);
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-bf[1][j], af[1][i], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[0][j], af[1][i], acc[1][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[1][j], af[0][i], acc[1][i][j], 0, 0, 0);
+          } else {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[0][j], af[0][i], acc[0][i][j], 0, 0, 0);
+          }
+        }
     }
   };
   const int nk = (Ki + KC - 1) / KC;
@@ -673,7 +721,10 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
       for (int r = 0; r < 4; ++r) {
         const int q = q0 + wq0 + j * 16 + 4 * lk + r;
         if (q >= Qi) continue;
-        lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[i][j][r]);
+        if constexpr (CPLX)
+          lp_store_c<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[0][i][j][r], acc[1][i][j][r]);
+        else
+          lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[0][i][j][r]);
       }
   }
 }
@@ -886,12 +937,36 @@ int launch_lp_prec(bool v32, GemmArgs& g, bool mode1, hipStream_t s) {
              : launch_lp_typed<PREC, double, double, OUT32, false>(g, s);
 }
 
+// complex data, FP32 contraction (complex64 arithmetic): 4 FP32 MFMAs per block
+template <typename TA, typename TB, bool OUT32, bool BK>
+int launch_c64_typed(GemmArgs& g, hipStream_t s) {
+  constexpr int TM = 64, TQ = 64;
+  g.tiles_m = (g.M + TM - 1) / TM;
+  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  const long nt = g.tiles_m * g.tiles_q * g.batches;
+  if (nt <= 0) return EXPINT_OK;
+  if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
+  hipLaunchKernelGGL((k_mode_product_f32<TA, TB, OUT32, BK, TM, TQ, 16, 2, 4>), dim3((unsigned)nt), dim3(512), 0, s, g);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
+  return EXPINT_OK;
+}
+
+template <bool OUT32>
+int launch_c64(bool v32, GemmArgs& g, bool mode1, hipStream_t s) {
+  if (mode1)
+    return v32 ? launch_c64_typed<cdouble, cfloat, OUT32, true>(g, s)
+               : launch_c64_typed<cdouble, cdouble, OUT32, true>(g, s);
+  return v32 ? launch_c64_typed<cfloat, cdouble, OUT32, false>(g, s)
+             : launch_c64_typed<cdouble, cdouble, OUT32, false>(g, s);
+}
+
 }  // namespace
 
-int launch_mode_product_lp(int precision, bool v32, bool out32, long s, int n, long r, const void* M,
+int launch_mode_product_lp(int precision, bool cplx, bool v32, bool out32, long s, int n, long r, const void* M,
                            const void* V, const Epilogue& epi, void* stream) {
   if (s <= 0 || n <= 0 || r <= 0) return EXPINT_OK;
-  const long bytes = s * (long)n * r * 8;
+  const long bytes = s * (long)n * r * (cplx ? 16 : 8);
   if (bytes >= (1L << 31))
     return set_error(EXPINT_ENOTSUP, "mode product: tensors of %ld bytes exceed the 2 GiB limit", bytes);
   if (out32 && (epi.op != EPI_AXPBY || epi.alpha != 1.0 || epi.beta != 0.0))
@@ -906,6 +981,11 @@ int launch_mode_product_lp(int precision, bool v32, bool out32, long s, int n, l
   } else {
     g.A = V; g.lda = s; g.B = M; g.bk = n; g.bq = 1;
     g.M = s; g.Q = n; g.K = n; g.sA = s * (long)n; g.sC = s * (long)n; g.ldc = s; g.batches = r;
+  }
+  if (cplx) {
+    if (precision != EXPINT_PREC_FP32)
+      return set_error(EXPINT_ENOTSUP, "complex data: reduced precision is FP32 (complex64) only");
+    return out32 ? launch_c64<true>(v32, g, mode1, st) : launch_c64<false>(v32, g, mode1, st);
   }
   if (precision == EXPINT_PREC_FP32)
     return out32 ? launch_lp_prec<EXPINT_PREC_FP32, true>(v32, g, mode1, st)
