@@ -319,7 +319,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
-                 {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)"}[args.precision],
+                 ("c64 (state c128)" if p.is_complex else
+                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)"}[args.precision]),
         "data": "synthetic",
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
                    "precision": args.precision, "graph": True},
@@ -337,6 +338,19 @@ def main():
         d = (U - Uref).abs().max().item() / Uref.abs().max().item()
         result["rel_err_vs_fp64"] = d
         ref_plan.close()
+    if p.g == "cubic_nls":
+        # Lawson-Euler with a unitary e^{tau A}: sum|U_{n+1}|^2 = sum|U_n|^2 (1 + tau^2 |U_n|^4)
+        Um = U0.clone()
+        worst = 0.0
+        for _ in range(10):
+            prev = Um.clone()
+            plan.step(Um)
+            torch.cuda.synchronize()
+            a2 = prev.abs() ** 2
+            lhs = (Um.abs() ** 2).sum().item()
+            rhs = (a2 * (1 + p.tau ** 2 * a2 * a2)).sum().item()
+            worst = max(worst, abs(lhs - rhs) / rhs)
+        result["mass_identity_max_rel_residual_10_steps"] = worst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
     plan.close()
