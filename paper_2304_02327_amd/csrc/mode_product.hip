@@ -120,7 +120,7 @@ __device__ __forceinline__ cdouble buffer_ld<cdouble>(__amdgpu_buffer_rsrc_t r, 
 // One TM x TQ output tile (tile index T_ in [0, tiles_m tiles_q batches)) of the
 // GEMM described by g, computed by the whole workgroup.  Used by the single
 // launch below and by the persistent grouped launch.
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   constexpr bool CPLX = std::is_same<T, cdouble>::value;
   constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
@@ -255,35 +255,28 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
     }
   };
 
-  // Two register sets keep two K chunks in flight: while LDS buffer c is
-  // consumed, chunk k+1 travels into the other register set and chunk k+2 is
-  // requested.  Loads inside the steady-state loop are unconditional (a chunk
-  // past the end reads zeros), so the outstanding-load count is the same on
-  // every path and the compiler waits only for the chunk it is about to
-  // store.  One barrier per chunk.
+  // PF register sets keep PF K chunks in flight.  At step c the LDS buffer
+  // c mod 2 holds chunk c, the sets hold chunks c+1 .. c+PF-1, and the set
+  // that held chunk c (already stored) requests chunk c+PF.  Loads are
+  // unconditional: a chunk past the end reads zeros from outside the buffer
+  // range without touching memory, so the outstanding-load count is the same
+  // on every path and each store waits only for its own chunk.  One barrier
+  // per chunk.
   const int nk = (Ki + KC - 1) / KC;
-  T ra0[AL], rb0[BL], ra1[AL], rb1[BL];
-  gload(ra0, rb0, 0);
-  gload(ra1, rb1, KC);
-  sstore(ra0, rb0, 0);
+  T ra[PF][AL], rb[PF][BL];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) gload(ra[u], rb[u], u * KC);
+  sstore(ra[0], rb[0], 0);
   __syncthreads();
-  int kc = 0;
-  for (; kc + 2 < nk; kc += 2) {
-    gload(ra0, rb0, (kc + 2) * KC);
-    compute(0);
-    sstore(ra1, rb1, 1);
-    __syncthreads();
-    gload(ra1, rb1, (kc + 3) * KC);
-    compute(1);
-    sstore(ra0, rb0, 0);
-    __syncthreads();
-  }
-  // tail: one or two chunks left; buffer 0 holds chunk kc, ra1 chunk kc + 1
-  compute(0);
-  if (kc + 1 < nk) {
-    sstore(ra1, rb1, 1);
-    __syncthreads();
-    compute(1);
+  for (int kc = 0; kc < nk; kc += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = kc + u;
+      gload(ra[u], rb[u], (c + PF) * KC);
+      if (c < nk) compute(c & 1);
+      if (c + 1 < nk) sstore(ra[(u + 1) % PF], rb[(u + 1) % PF], (c + 1) & 1);
+      __syncthreads();
+    }
   }
 
   // acc[.][i][j][r] holds C[m, q] with m = wm0 + 16 i + (lane mod 16),
@@ -308,10 +301,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   }
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF>
 __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
   const long nt = g.tiles_m * g.tiles_q * g.batches;
-  gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ>(g, xcd_remap((long)blockIdx.x, nt));
+  gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ, PF>(g, xcd_remap((long)blockIdx.x, nt));
 }
 
 // Persistent grouped GEMM: `count` independent GEMMs (one descriptor each,
@@ -336,15 +329,15 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_grouped_gemm(const GemmArgs*
   }
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2>
 int launch_tile(GemmArgs& g, hipStream_t s) {
   g.tiles_m = (g.M + TM - 1) / TM;
   g.tiles_q = (g.Q + TQ - 1) / TQ;
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
-  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC, WGM, WGQ>), dim3((unsigned)nt), dim3(64 * WGM * WGQ), 0,
-                     s, g);
+  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC, WGM, WGQ, PF>), dim3((unsigned)nt), dim3(64 * WGM * WGQ),
+                     0, s, g);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
@@ -352,8 +345,9 @@ int launch_tile(GemmArgs& g, hipStream_t s) {
 
 // Tile configurations (TM x TQ outputs per workgroup; "w8" = 8 waves, else 4).
 // EXPINT_TILE set to one of these names overrides the automatic choice.
-const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128",
-                                  "32x32", "64x64w8", "128x64w8", "128x128w8", "128x128"};
+const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128", "32x32",
+                                  "64x64w8", "128x64w8", "128x128w8", "128x128", "128x64w8k32", "128x128w8k32",
+                                  "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4"};
 constexpr int kNumTiles = sizeof(kTileNames) / sizeof(kTileNames[0]);
 
 int tile_override() {
@@ -390,6 +384,12 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
     case 7: return launch_tile<T, BK, 128, 64, KCR, 4, 2>(g, st);
     case 8: return launch_tile<T, BK, 128, 128, KCR, 4, 2>(g, st);
     case 9: return launch_tile<T, BK, 128, 128, KCR, 2, 2>(g, st);
+    case 10: return launch_tile<T, BK, 128, 64, KCR * 2, 4, 2>(g, st);
+    case 11: return launch_tile<T, BK, 128, 128, KCR * 2, 4, 2>(g, st);
+    case 12: return launch_tile<T, BK, 128, 64, KCR, 4, 2, 3>(g, st);
+    case 13: return launch_tile<T, BK, 128, 64, KCR, 4, 2, 4>(g, st);
+    case 14: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 3>(g, st);
+    case 15: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 4>(g, st);
     default: return launch_tile<T, BK, 64, 64, KCR, 2, 2>(g, st);
   }
 }
