@@ -62,6 +62,10 @@ extern "C" {
 #define EXPINT_G_ALLEN_CAHN  1  /* g = u - u^3 */
 #define EXPINT_G_U2_1MU      2  /* g = u^2 (1 - u) */
 #define EXPINT_G_CUBIC_NLS   3  /* g = -i kappa |u|^2 u (complex only; kappa = g_param) */
+#define EXPINT_G_ADR_PAPER   4  /* g(t, x, u) = 1/(1 + u^2) + Psi(t, x): the manufactured source of the
+                                   advection-diffusion-reaction test of section 4.2 (eq. ADR) on the inner
+                                   grid x_mu = (i + 1)/(n_mu + 1), d = 3, eps = g_param, alpha = g_param2;
+                                   non-autonomous: uses t */
 
 /* ------------------------------------------------------------------------ */
 /* phi_setup: the small matrices phi_l(tau A) of one direction               */
@@ -137,7 +141,8 @@ typedef struct expint_problem {
   double tau;            /* constant step size */
   int scheme;            /* EXPINT_LAWSON_EULER .. EXPINT_ETD2RK */
   int nonlin;            /* EXPINT_G_* */
-  double g_param;        /* kappa of EXPINT_G_CUBIC_NLS, unused otherwise */
+  double g_param;        /* kappa of EXPINT_G_CUBIC_NLS, eps of EXPINT_G_ADR_PAPER */
+  double g_param2;       /* alpha of EXPINT_G_ADR_PAPER */
   int dtype;             /* EXPINT_F64 or EXPINT_C128 */
   int precision;         /* contraction precision of the Tucker operators (EXPINT_PREC_*;
                             reduced precision for real data only); K u, g and the

@@ -26,7 +26,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, C128 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 SCHEMES = {"lawson_euler": 0, "lawson2b": 1, "exp_euler": 2, "etd2rk": 3}
-NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3}
+NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3, "adr_paper": 4}
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
 
 
@@ -92,6 +92,7 @@ class _Problem(ctypes.Structure):
         ("scheme", ctypes.c_int),
         ("nonlin", ctypes.c_int),
         ("g_param", ctypes.c_double),
+        ("g_param2", ctypes.c_double),
         ("dtype", ctypes.c_int),
         ("precision", ctypes.c_int),
     ]
@@ -232,7 +233,7 @@ class Plan:
     """
 
     def __init__(self, A: Sequence[np.ndarray], tau: float, scheme: str, nonlin: str,
-                 g_param: float = 0.0, precision: str = "fp64", device="cuda"):
+                 g_param: float = 0.0, precision: str = "fp64", device="cuda", g_param2: float = 0.0):
         import torch
         A = [np.asarray(a) for a in A]
         cplx = any(np.iscomplexobj(a) for a in A) or nonlin == "cubic_nls"
@@ -254,6 +255,7 @@ class Plan:
         prob.scheme = SCHEMES[scheme]
         prob.nonlin = NONLIN[nonlin]
         prob.g_param = float(g_param)
+        prob.g_param2 = float(g_param2)
         prob.dtype = self.dtype
         prob.precision = PRECISIONS[precision]
         self._handle = ctypes.c_void_p(None)

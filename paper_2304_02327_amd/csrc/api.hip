@@ -215,6 +215,10 @@ struct expint_plan {
   Stencil stencil;                   // device coefficient arrays when use_stencil
   void* denseA[4] = {};              // device A_mu for the dense K u path
   int device = 0;
+  // coordinate / time dependent nonlinearity
+  GridTime gt;
+  double* d_clock = nullptr;
+  bool timedep = false;
   // cached graph of one step
   hipGraphExec_t gexec = nullptr;
   const void* g_U = nullptr;
@@ -254,6 +258,7 @@ void free_plan_memory(expint_plan* p) {
     if (p->denseA[mu]) (void)hipFree(p->denseA[mu]);
   }
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->d_clock) (void)hipFree(p->d_clock);
 }
 
 int scheme_phi_range(int scheme, int* lo, int* hi) {
@@ -298,8 +303,8 @@ int workspace_elems(const expint_plan* p, long* elems) {
 // stage input W = tau (K U + g(U))
 int stage_input(expint_plan* p, const void* U, void* W, hipStream_t s) {
   if (p->use_stencil)
-    return launch_stage_stencil(p->dtype, p->stencil, p->N, U, W, p->tau, p->nonlin, p->gparam, s);
-  TRY(launch_scaled_g(p->dtype, p->N, U, W, p->tau, p->nonlin, p->gparam, s));
+    return launch_stage_stencil(p->dtype, p->stencil, p->N, U, W, p->tau, p->nonlin, p->gparam, p->gt, s);
+  TRY(launch_scaled_g(p->dtype, p->N, U, W, p->tau, p->nonlin, p->gparam, p->gt, s));
   for (int mu = 0; mu < p->d; ++mu) {
     long sv, rv;
     mode_view(p->d, p->n, mu, &sv, &rv);
@@ -313,7 +318,16 @@ int stage_input(expint_plan* p, const void* U, void* W, hipStream_t s) {
   return EXPINT_OK;
 }
 
+int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s);
+
+// one step; a time-dependent g also advances the device clock at the end
 int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
+  TRY(enqueue_step_body(p, U, ws, s));
+  if (p->timedep) TRY(launch_clock_tick(p->d_clock, s));
+  return EXPINT_OK;
+}
+
+int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
   const size_t es = elem_size(p->dtype);
   char* base = static_cast<char*>(ws);
   void* W = base;
@@ -328,7 +342,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
   switch (p->scheme) {
     case EXPINT_LAWSON_EULER: {
       // U_{n+1} = (U_n + tau G_n) x_mu e^{tau A_mu}
-      TRY(launch_lawson_stage(p->dtype, p->N, U, W, nullptr, p->tau, p->nonlin, p->gparam, s));
+      TRY(launch_lawson_stage(p->dtype, p->N, U, W, nullptr, p->tau, p->nonlin, p->gparam, p->gt, s));
       Epilogue e;
       e.op = EPI_AXPBY;
       e.out0 = U;
@@ -336,7 +350,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
     }
     case EXPINT_LAWSON2B: {
       // U_n2 = (U_n + tau G_n) x e^{tau A};  U_{n+1} = (U_n + tau/2 G_n) x e^{tau A} + tau/2 G(U_n2)
-      TRY(launch_lawson_stage(p->dtype, p->N, U, W, X, p->tau, p->nonlin, p->gparam, s));
+      TRY(launch_lawson_stage(p->dtype, p->N, U, W, X, p->tau, p->nonlin, p->gparam, p->gt, s));
       Epilogue e1;
       e1.op = EPI_AXPBY;
       e1.out0 = Y;
@@ -348,6 +362,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e2.c = 0.5 * p->tau;
       e2.g = p->nonlin;
       e2.gparam = p->gparam;
+      e2.gt = p->gt;
       return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, X, T0, T1, e2, s);
     }
     case EXPINT_EXP_EULER: {
@@ -371,6 +386,7 @@ int enqueue_step(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e1.tau = p->tau;
       e1.g = p->nonlin;
       e1.gparam = p->gparam;
+      e1.gt = p->gt;
       if (count_modes(p->d, P1) == 1) {
         // a single mode reads W while its epilogue writes W_2: keep them apart
         e1.out1 = T1;
@@ -416,8 +432,10 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if (cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_CUBIC_NLS)
     return set_error(EXPINT_ENOTSUP, "complex data supports g = NONE or CUBIC_NLS");
   if (!cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_ALLEN_CAHN &&
-      prob->nonlin != EXPINT_G_U2_1MU)
-    return set_error(EXPINT_ENOTSUP, "real data supports g = NONE, ALLEN_CAHN or U2_1MU");
+      prob->nonlin != EXPINT_G_U2_1MU && prob->nonlin != EXPINT_G_ADR_PAPER)
+    return set_error(EXPINT_ENOTSUP, "real data supports g = NONE, ALLEN_CAHN, U2_1MU or ADR_PAPER");
+  if (prob->nonlin == EXPINT_G_ADR_PAPER && prob->d != 3)
+    return set_error(EXPINT_ENOTSUP, "EXPINT_G_ADR_PAPER is defined for d = 3");
   int lo, hi;
   TRY(scheme_phi_range(prob->scheme, &lo, &hi));
   for (int mu = 0; mu < prob->d; ++mu)
@@ -432,6 +450,14 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   p->scheme = prob->scheme;
   p->nonlin = prob->nonlin;
   p->gparam = prob->g_param;
+  p->timedep = prob->nonlin == EXPINT_G_ADR_PAPER;
+  for (int mu = 0; mu < 3 && mu < prob->d; ++mu) {
+    p->gt.n[mu] = prob->n[mu];
+    p->gt.h[mu] = 1.0 / (prob->n[mu] + 1);
+  }
+  p->gt.eps = prob->g_param;
+  p->gt.alpha = prob->g_param2;
+  p->gt.tau = prob->tau;
   p->dtype = prob->dtype;
   p->precision = prob->precision;
   p->ell_lo = lo;
@@ -543,6 +569,16 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
       }
     }
   }
+  if (rc == EXPINT_OK && p->timedep) {
+    if (hipMalloc(&p->d_clock, 2 * sizeof(double)) != hipSuccess) {
+      rc = set_error(EXPINT_ENOMEM, "device allocation for the clock failed");
+    } else {
+      const double zero[2] = {0.0, 0.0};
+      if (hipMemcpy(p->d_clock, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+        rc = set_error(EXPINT_EHIP, "clock initialisation failed");
+      p->gt.clock = p->d_clock;
+    }
+  }
   if (rc != EXPINT_OK) {
     free_plan_memory(p);
     delete p;
@@ -583,17 +619,20 @@ extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double
 }
 
 extern "C" int expint_step(expint_plan* p, void* U, double t, void* ws, void* stream) {
-  (void)t;  // the supported nonlinearities are autonomous
   TRY(validate_step_args(p, U, ws));
+  if (!std::isfinite(t)) return set_error(EXPINT_EINVAL, "t is not finite");
+  if (p->timedep) TRY(launch_clock_set(p->d_clock, t, stream));
   return enqueue_step(p, U, ws, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int expint_run(expint_plan* p, void* U, double t0, int nsteps, int use_graph, void* ws,
                           void* stream) {
-  (void)t0;
   TRY(validate_step_args(p, U, ws));
   if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps < 0");
+  if (!std::isfinite(t0)) return set_error(EXPINT_EINVAL, "t0 is not finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // t_n = t0 + n tau for the steps below (the captured step advances n)
+  if (p->timedep) TRY(launch_clock_set(p->d_clock, t0, s));
   if (!use_graph) {
     for (int k = 0; k < nsteps; ++k) TRY(enqueue_step(p, U, ws, s));
     return EXPINT_OK;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/expint.h"
+#include "internal.h"
 
 namespace expint {
 
@@ -29,6 +30,56 @@ __device__ __forceinline__ cdouble scale(cdouble a, double s) { return cdouble{a
 __device__ __forceinline__ double fma_t(double c, double x, double acc) { return fma(c, x, acc); }
 __device__ __forceinline__ cdouble fma_t(cdouble c, cdouble x, cdouble acc) {
   return cdouble{fma(c.re, x.re, fma(-c.im, x.im, acc.re)), fma(c.re, x.im, fma(c.im, x.re, acc.im))};
+}
+
+// Manufactured-solution nonlinearity of the paper's advection-diffusion-
+// reaction test (section 4.2, eq. ADR): g = 1/(1 + u^2) + Psi(t, x) with Psi
+// such that u = e^t 64 prod_mu x_mu (1 - x_mu) solves
+// u_t = eps Laplace(u) + alpha sum_mu d_mu u + g.  With q = x (1 - x), q' = 1 - 2x,
+// q'' = -2:  Psi = u - eps e^t 64 sum_mu q''_mu prod_{nu != mu} q_nu
+//                 - alpha e^t 64 sum_mu q'_mu prod_{nu != mu} q_nu - 1/(1 + u^2).
+// x_mu = (i_mu + 1) h_mu on the inner grid, h_mu = 1/(n_mu + 1).
+
+__device__ __forceinline__ double adr_paper_g(const GridTime& c, double u, double t, int i1, int i2, int i3) {
+  const double x1 = (i1 + 1) * c.h[0], x2 = (i2 + 1) * c.h[1], x3 = (i3 + 1) * c.h[2];
+  const double q1 = x1 * (1.0 - x1), q2 = x2 * (1.0 - x2), q3 = x3 * (1.0 - x3);
+  const double d1 = 1.0 - 2.0 * x1, d2 = 1.0 - 2.0 * x2, d3 = 1.0 - 2.0 * x3;
+  const double e = exp(t) * 64.0;
+  const double ue = e * q1 * q2 * q3;
+  const double lap = e * (-2.0) * (q2 * q3 + q1 * q3 + q1 * q2);
+  const double adv = e * (d1 * q2 * q3 + q1 * d2 * q3 + q1 * q2 * d3);
+  const double psi = ue - c.eps * lap - c.alpha * adv - 1.0 / (1.0 + ue * ue);
+  return 1.0 / (1.0 + u * u) + psi;
+}
+
+__device__ __forceinline__ double clock_time(const GridTime& c, double ahead) {
+  return c.clock[0] + c.clock[1] * c.tau + ahead;
+}
+
+// g at tensor element e (layout i1 + n1 (i2 + n2 i3)), time t_n + ahead
+__device__ __forceinline__ double g_at(int g, double u, double gparam, const GridTime& gt, long e, double ahead) {
+  if (g == EXPINT_G_ADR_PAPER) {
+    const int i1 = (int)(e % gt.n[0]);
+    const long r = e / gt.n[0];
+    const int i2 = (int)(r % gt.n[1]);
+    const int i3 = (int)(r / gt.n[1]);
+    return adr_paper_g(gt, u, clock_time(gt, ahead), i1, i2, i3);
+  }
+  switch (g) {
+    case EXPINT_G_ALLEN_CAHN:
+      return u - u * u * u;
+    case EXPINT_G_U2_1MU:
+      return u * u * (1.0 - u);
+    default:
+      return 0.0;
+  }
+}
+__device__ __forceinline__ cdouble g_at(int g, cdouble u, double gparam, const GridTime&, long, double) {
+  if (g == EXPINT_G_CUBIC_NLS) {
+    const double m = gparam * (u.re * u.re + u.im * u.im);
+    return cdouble{m * u.im, -m * u.re};
+  }
+  return cdouble{0.0, 0.0};
 }
 
 // g(u) for the autonomous nonlinearities of the workloads

@@ -20,6 +20,17 @@ void phi_setup_single_threaded(bool on);
 // mu-mode product launcher
 // ---------------------------------------------------------------------------
 
+// Grid and clock of a coordinate- and time-dependent nonlinearity
+// (EXPINT_G_ADR_PAPER): x_mu = (i_mu + 1) h_mu; t_n = clock[0] + clock[1] tau
+// with clock a device pair {t0, steps taken} advanced by a kernel each step.
+struct GridTime {
+  int n[3] = {1, 1, 1};
+  double h[3] = {0.0, 0.0, 0.0};
+  double eps = 0.0, alpha = 0.0;
+  const double* clock = nullptr;
+  double tau = 0.0;
+};
+
 // What the last stage of a mu-mode product does with its result Y (per
 // element e of the tensor; every tensor shares the layout of Y).
 enum EpiOp : int {
@@ -39,6 +50,7 @@ struct Epilogue {
   const void* in1 = nullptr;   // secondary input
   const void* in2 = nullptr;   // third input (EPI_LINEAR)
   void* out1 = nullptr;        // secondary output
+  GridTime gt;                 // for EXPINT_G_ADR_PAPER
 };
 
 // Y = V x_mu M for a tensor viewed as (s, n, r): s = prod_{nu<mu} n_nu (stride 1),
@@ -84,14 +96,17 @@ struct Stencil {
   double tc[4][3][2] = {};
 };
 
-// W = tau * (K U + g(U)) with K applied as the stencil.
+// W = tau * (K U + g(t_n, U)) with K applied as the stencil.
 int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, void* W,
-                         double tau, int g, double gparam, void* stream);
-// W = a * g(U) (no K term; the dense path adds tau * U x_mu A_mu afterwards)
+                         double tau, int g, double gparam, const GridTime& gt, void* stream);
+// W = a * g(t_n, U) (no K term; the dense path adds tau * U x_mu A_mu afterwards)
 int launch_scaled_g(int dtype, long N, const void* U, void* W, double a, int g, double gparam,
-                    void* stream);
-// Wa = U + tau g(U); Wb = U + tau/2 g(U) (Wb may be NULL)
+                    const GridTime& gt, void* stream);
+// Wa = U + tau g(t_n, U); Wb = U + tau/2 g(t_n, U) (Wb may be NULL)
 int launch_lawson_stage(int dtype, long N, const void* U, void* Wa, void* Wb, double tau, int g,
-                        double gparam, void* stream);
+                        double gparam, const GridTime& gt, void* stream);
+// clock = {t0, 0} / clock[1] += 1 (one thread; graph-capturable, no memset)
+int launch_clock_set(double* clock, double t0, void* stream);
+int launch_clock_tick(double* clock, void* stream);
 
 }  // namespace expint

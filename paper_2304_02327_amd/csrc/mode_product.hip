@@ -74,14 +74,16 @@ __device__ __forceinline__ void epilogue_store(const Epilogue& ep, long e, T y) 
       const T u = ld<T>(ep.in1, e);
       const T u2 = add(u, y);
       out0[e] = u2;
-      static_cast<T*>(ep.out1)[e] = scale(sub(g_eval(ep.g, u2, ep.gparam), g_eval(ep.g, u, ep.gparam)), ep.tau);
+      // W_2 = tau (g(t_{n+1}, U_n2) - g(t_n, U_n))
+      static_cast<T*>(ep.out1)[e] =
+          scale(sub(g_at(ep.g, u2, ep.gparam, ep.gt, e, ep.tau), g_at(ep.g, u, ep.gparam, ep.gt, e, 0.0)), ep.tau);
       break;
     }
     case EPI_ETD2RK_2:
       out0[e] = add(ld<T>(ep.in1, e), scale(y, ep.c));
       break;
-    case EPI_LAWSON2B_2:
-      out0[e] = add(y, scale(g_eval(ep.g, ld<T>(ep.in1, e), ep.gparam), ep.c));
+    case EPI_LAWSON2B_2:  // U_{n+1} = Y + tau/2 g(t_{n+1}, U_n2)
+      out0[e] = add(y, scale(g_at(ep.g, ld<T>(ep.in1, e), ep.gparam, ep.gt, e, 2.0 * ep.c), ep.c));
       break;
     case EPI_LINEAR: {
       T v = scale(y, ep.alpha);

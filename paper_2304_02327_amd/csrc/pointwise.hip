@@ -5,6 +5,8 @@
 // writes its outputs once.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -25,6 +27,7 @@ struct StencilArgs {
   double tau;
   int g;
   double gparam;
+  GridTime gt;
 };
 
 // Workgroups are dealt round-robin over the 8 XCDs.  Remapping block L so that
@@ -54,6 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
   const T u = U[e];
   T acc = zero<T>();
   unsigned rem = e, stride = 1;
+  int idx[3] = {0, 0, 0};
 #pragma unroll
   for (int mu = 0; mu < D; ++mu) {
     const unsigned nm = (unsigned)a.n[mu];
@@ -64,6 +68,7 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
     } else {
       i = rem;
     }
+    idx[mu] = (int)i;
     const T* c = static_cast<const T*>(a.coef[mu]);
     const T clo = TOEP ? tcoef<T>(a.tc[mu][0]) : c[i];
     const T cdi = TOEP ? tcoef<T>(a.tc[mu][1]) : c[nm + i];
@@ -79,24 +84,33 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
       acc = fma_t(cup, U[e - (nm - 1) * stride], acc);
     stride *= nm;
   }
-  static_cast<T*>(a.W)[e] = scale(add(acc, g_eval(a.g, u, a.gparam)), a.tau);
+  T gu;
+  if constexpr (std::is_same<T, double>::value) {
+    if (D == 3 && a.g == EXPINT_G_ADR_PAPER)
+      gu = adr_paper_g(a.gt, u, clock_time(a.gt, 0.0), idx[0], idx[1], idx[2]);
+    else
+      gu = g_eval(a.g, u, a.gparam);
+  } else {
+    gu = g_eval(a.g, u, a.gparam);
+  }
+  static_cast<T*>(a.W)[e] = scale(add(acc, gu), a.tau);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scaled_g(long N, const void* Uv, void* Wv, double s,
-                                                       int g, double gp) {
+                                                       int g, double gp, GridTime gt) {
   const long e = (long)blockIdx.x * kThreads + threadIdx.x;
   if (e >= N) return;
-  static_cast<T*>(Wv)[e] = scale(g_eval(g, static_cast<const T*>(Uv)[e], gp), s);
+  static_cast<T*>(Wv)[e] = scale(g_at(g, static_cast<const T*>(Uv)[e], gp, gt, e, 0.0), s);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_lawson_stage(long N, const void* Uv, void* Wa, void* Wb,
-                                                           double tau, int g, double gp) {
+                                                           double tau, int g, double gp, GridTime gt) {
   const long e = (long)blockIdx.x * kThreads + threadIdx.x;
   if (e >= N) return;
   const T u = static_cast<const T*>(Uv)[e];
-  const T gu = g_eval(g, u, gp);
+  const T gu = g_at(g, u, gp, gt, e, 0.0);
   static_cast<T*>(Wa)[e] = add(u, scale(gu, tau));
   if (Wb) static_cast<T*>(Wb)[e] = add(u, scale(gu, 0.5 * tau));
 }
@@ -112,7 +126,7 @@ int check_launch(const char* what) {
 }  // namespace
 
 int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, void* W, double tau,
-                         int g, double gparam, void* stream) {
+                         int g, double gparam, const GridTime& gt, void* stream) {
   if (N <= 0) return EXPINT_OK;
   StencilArgs a;
   a.N = N;
@@ -129,6 +143,7 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
   a.tau = tau;
   a.g = g;
   a.gparam = gparam;
+  a.gt = gt;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(blocks_for(N)), block(kThreads);
   const bool c = dtype == EXPINT_C128;
@@ -158,27 +173,49 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
 }
 
 int launch_scaled_g(int dtype, long N, const void* U, void* W, double a, int g, double gparam,
-                    void* stream) {
+                    const GridTime& gt, void* stream) {
   if (N <= 0) return EXPINT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (dtype == EXPINT_C128)
-    hipLaunchKernelGGL(k_scaled_g<cdouble>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, W, a, g, gparam);
+    hipLaunchKernelGGL(k_scaled_g<cdouble>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, W, a, g, gparam, gt);
   else
-    hipLaunchKernelGGL(k_scaled_g<double>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, W, a, g, gparam);
+    hipLaunchKernelGGL(k_scaled_g<double>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, W, a, g, gparam, gt);
   return check_launch("scaled_g");
 }
 
 int launch_lawson_stage(int dtype, long N, const void* U, void* Wa, void* Wb, double tau, int g,
-                        double gparam, void* stream) {
+                        double gparam, const GridTime& gt, void* stream) {
   if (N <= 0) return EXPINT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (dtype == EXPINT_C128)
     hipLaunchKernelGGL(k_lawson_stage<cdouble>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, Wa, Wb,
-                       tau, g, gparam);
+                       tau, g, gparam, gt);
   else
     hipLaunchKernelGGL(k_lawson_stage<double>, dim3(blocks_for(N)), dim3(kThreads), 0, s, N, U, Wa, Wb,
-                       tau, g, gparam);
+                       tau, g, gparam, gt);
   return check_launch("lawson_stage");
+}
+
+namespace {
+__global__ void k_clock_set(double* clock, double t0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    clock[0] = t0;
+    clock[1] = 0.0;
+  }
+}
+__global__ void k_clock_tick(double* clock) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[1] += 1.0;
+}
+}  // namespace
+
+int launch_clock_set(double* clock, double t0, void* stream) {
+  hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), clock, t0);
+  return check_launch("clock_set");
+}
+
+int launch_clock_tick(double* clock, void* stream) {
+  hipLaunchKernelGGL(k_clock_tick, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), clock);
+  return check_launch("clock_tick");
 }
 
 }  // namespace expint

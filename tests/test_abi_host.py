@@ -118,7 +118,7 @@ def test_tucker_workspace_size_and_validation():
     assert B.lib.tucker_apply(2, n, ptrs, None, None, 1.0, 0.0, 0, 0, None, 0, None) == B.EINVAL
     assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 7, 0, None, 0, None) == B.EINVAL
     assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 0, 5, None, 0, None) == B.EINVAL  # unknown precision
-    assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 1, 1, None, 0, None) == B.ENOTSUP  # complex + FP32
+    assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 1, 2, None, 0, None) == B.ENOTSUP  # complex + bf16x3
     # every matrix NULL
     assert B.lib.tucker_apply(2, n, ptrs, 16, 32, 1.0, 0.0, 0, 0, None, 0, None) == B.EINVAL
 
@@ -145,10 +145,18 @@ def test_plan_create_rejects_bad_problems():
     prob.nonlin = 2
     prob.precision = 7
     assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.EINVAL
-    prob.precision = 1
+    prob.nonlin = 4  # the manufactured ADR source is three-dimensional
+    prob.precision = 0
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
+    assert "d = 3" in B.lib.expint_last_error().decode()
+    prob.precision = 2
     prob.dtype = 1
     prob.nonlin = 3
-    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP  # complex + FP32
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP  # complex + bf16x3
+    prob.precision = 0
+    prob.nonlin = 4
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP  # complex + ADR source
+    assert h.value is None
     assert B.lib.expint_step(None, None, 0.0, None, None) == B.EINVAL
 
 
