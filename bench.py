@@ -44,9 +44,34 @@ def make_workload(name: str):
     elif name == "dr384":
         p = W.diffusion_reaction_3d(n=384)
         desc = "3-D diffusion-reaction 384^3, ETD2RK phisplit, FP64, tau=2e-3"
+    elif name in PAPER_RUNS:
+        n, steps, _, _ = PAPER_RUNS[name]
+        p = W.adr_paper(n, steps=steps, scheme="etd2rk")
+        desc = (f"section 4.2 ADR {n[0]}x{n[1]}x{n[2]} (eps=0.75, alpha=0.1, manufactured source), "
+                f"ETD2RK phisplit, {steps} steps to T=1, FP64")
     else:
         raise SystemExit(f"unknown workload {name}")
     return p, desc
+
+
+# The paper's ETD2RK phisplit runs of the section 4.2 ADR problem at the finest step
+# size of its order study (Figures adr_ord12_40 and adr_ord12): grid, steps, wall
+# clock in seconds and the printed relative infinity-norm error at T = 1.  Measured
+# in MATLAB R2022a on an Intel Core i7-10750H (6 cores), FP64.
+PAPER_RUNS = {
+    "adr_paper40": ((40, 41, 42), 440, 0.4505, 2.14158850419228e-06),
+    "adr_paper80": ((80, 81, 82), 440, 7.8158, 2.14108285352612e-06),
+}
+PAPER_HW = "MATLAB R2022a, Intel Core i7-10750H (6 cores), FP64"
+
+
+def plan_kwargs(p):
+    """Nonlinearity parameters of a workload as the plan takes them."""
+    if p.g == "cubic_nls":
+        return {"g_param": p.g_params.get("kappa", 0.0)}
+    if p.g == "adr_paper":
+        return {"g_param": p.g_params["eps"], "g_param2": p.g_params["alpha"]}
+    return {}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mode_product_adr128_hbm_traffic.md")
@@ -182,7 +207,8 @@ def bench_riccati(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 100; the paper's step count for adr_paper*)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="adr128")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -211,16 +237,21 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     p, desc = make_workload(args.workload)
-    g_param = p.g_params.get("kappa", 0.0) if p.g == "cubic_nls" else 0.0
-    plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param, precision=args.precision)
+    if args.steps is None:
+        args.steps = p.steps if args.workload in PAPER_RUNS else 100
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    plan = px.Plan(p.A, p.tau, p.scheme, p.g, precision=args.precision, **plan_kwargs(p))
     U0 = px.tensor_to_device(p.u0, device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
     U = U0.clone()
     stream = torch.cuda.Stream()  # default priority
     stream.wait_stream(torch.cuda.current_stream())
 
     # warmup (includes the one-time graph capture)
     with torch.cuda.stream(stream):
-        plan.run(U, args.warmup, use_graph=True, stream=stream)
+        plan.run(U, args.warmup, t0=0.0, use_graph=True, stream=stream)
     stream.synchronize()
     U.copy_(U0)
     torch.cuda.synchronize()
@@ -232,7 +263,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     with torch.cuda.stream(stream):
-        plan.run(U, args.steps, use_graph=True, stream=stream)
+        plan.run(U, args.steps, t0=0.0, use_graph=True, stream=stream)
     ev1.record(stream)
     stream.synchronize()
     torch.cuda.synchronize()
@@ -329,9 +360,24 @@ def main():
         "roofline": roofline,
     }
 
+    if args.workload in PAPER_RUNS and args.steps == p.steps:
+        # the whole integration to T = 1, against the paper's run of the same problem
+        _, _, paper_s, paper_err = PAPER_RUNS[args.workload]
+        exact = math.exp(1.0) * np.asarray(p.u0)  # the manufactured solution e^t u0 at t = 1
+        Uh = px.tensor_from_device(U)
+        err = float(np.abs(Uh - exact).max() / np.abs(exact).max())
+        paper_value = p.N * p.steps / paper_s
+        result["vs_baseline"] = value / paper_value
+        result["paper_run"] = {
+            "hardware": PAPER_HW, "seconds": paper_s, "steps": p.steps,
+            "dof_steps_per_s": paper_value, "rel_err_inf_printed": paper_err,
+        }
+        result["rel_err_inf_vs_exact_at_T"] = err
+        result["seconds_setup_plus_steps"] = setup_s + gpu_ms / 1e3
+        result["setup_s_phi_on_host_and_upload"] = setup_s
     if args.precision != "fp64":
         # error of the reduced-precision run against the FP64 path after the same steps
-        ref_plan = px.Plan(p.A, p.tau, p.scheme, p.g, g_param=g_param)
+        ref_plan = px.Plan(p.A, p.tau, p.scheme, p.g, **plan_kwargs(p))
         Uref = U0.clone()
         ref_plan.run(Uref, args.steps)
         torch.cuda.synchronize()

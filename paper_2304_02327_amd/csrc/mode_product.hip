@@ -57,41 +57,54 @@ __device__ __forceinline__ long xcd_remap(long L, long nt) {
 template <typename T>
 __device__ __forceinline__ T ld(const void* p, long i) { return static_cast<const T*>(p)[i]; }
 
-template <typename T>
-__device__ __forceinline__ void epilogue_store(const Epilogue& ep, long e, T y) {
+// Applies the epilogue to the outputs a thread owns: visit(f) calls f(e, y)
+// for each of them.  The op and the nonlinearity are uniform per launch, so
+// they are dispatched once, outside the element loop: every path is a short
+// loop of its own and the code a launch runs stays compact.
+template <typename T, typename Visit>
+__device__ __forceinline__ void epilogue_tile(const Epilogue& ep, Visit&& visit) {
   T* out0 = static_cast<T*>(ep.out0);
   switch (ep.op) {
-    case EPI_AXPBY: {
-      T v = scale(y, ep.alpha);
-      if (ep.beta != 0.0) v = add(v, scale(out0[e], ep.beta));
-      out0[e] = v;
+    case EPI_AXPBY:
+      if (ep.beta != 0.0)
+        visit([&](long e, T y) { out0[e] = add(scale(y, ep.alpha), scale(out0[e], ep.beta)); });
+      else
+        visit([&](long e, T y) { out0[e] = scale(y, ep.alpha); });
       break;
-    }
     case EPI_EXP_EULER:
-      out0[e] = add(ld<T>(ep.in1, e), y);
+      visit([&](long e, T y) { out0[e] = add(ld<T>(ep.in1, e), y); });
       break;
-    case EPI_ETD2RK_1: {
-      const T u = ld<T>(ep.in1, e);
-      const T u2 = add(u, y);
-      out0[e] = u2;
-      // W_2 = tau (g(t_{n+1}, U_n2) - g(t_n, U_n))
-      static_cast<T*>(ep.out1)[e] =
-          scale(sub(g_at(ep.g, u2, ep.gparam, ep.gt, e, ep.tau), g_at(ep.g, u, ep.gparam, ep.gt, e, 0.0)), ep.tau);
+    case EPI_ETD2RK_1:
+      // U_n2 = U_n + Y and W_2 = tau (g(t_{n+1}, U_n2) - g(t_n, U_n))
+      dispatch_g(ep, T{}, [&](const auto& G) {
+        const auto g1 = G.at(ep.tau);
+        const auto g0 = G.at(0.0);
+        T* out1 = static_cast<T*>(ep.out1);
+        visit([&](long e, T y) {
+          const T u = ld<T>(ep.in1, e);
+          const T u2 = add(u, y);
+          out0[e] = u2;
+          out1[e] = scale(sub(g1(u2, e), g0(u, e)), ep.tau);
+        });
+      });
       break;
-    }
     case EPI_ETD2RK_2:
-      out0[e] = add(ld<T>(ep.in1, e), scale(y, ep.c));
+      visit([&](long e, T y) { out0[e] = add(ld<T>(ep.in1, e), scale(y, ep.c)); });
       break;
     case EPI_LAWSON2B_2:  // U_{n+1} = Y + tau/2 g(t_{n+1}, U_n2)
-      out0[e] = add(y, scale(g_at(ep.g, ld<T>(ep.in1, e), ep.gparam, ep.gt, e, 2.0 * ep.c), ep.c));
+      dispatch_g(ep, T{}, [&](const auto& G) {
+        const auto g1 = G.at(2.0 * ep.c);
+        visit([&](long e, T y) { out0[e] = add(y, scale(g1(ld<T>(ep.in1, e), e), ep.c)); });
+      });
       break;
-    case EPI_LINEAR: {
-      T v = scale(y, ep.alpha);
-      if (ep.in1) v = add(v, scale(ld<T>(ep.in1, e), ep.beta));
-      if (ep.in2) v = add(v, scale(ld<T>(ep.in2, e), ep.c));
-      out0[e] = v;
+    case EPI_LINEAR:
+      visit([&](long e, T y) {
+        T v = scale(y, ep.alpha);
+        if (ep.in1) v = add(v, scale(ld<T>(ep.in1, e), ep.beta));
+        if (ep.in2) v = add(v, scale(ld<T>(ep.in2, e), ep.c));
+        out0[e] = v;
+      });
       break;
-    }
     default:
       break;
   }
@@ -257,50 +270,79 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
     }
   };
 
-  // PF register sets keep PF K chunks in flight.  At step c the LDS buffer
-  // c mod 2 holds chunk c, the sets hold chunks c+1 .. c+PF-1, and the set
-  // that held chunk c (already stored) requests chunk c+PF.  Loads are
-  // unconditional: a chunk past the end reads zeros from outside the buffer
-  // range without touching memory, so the outstanding-load count is the same
-  // on every path and each store waits only for its own chunk.  One barrier
-  // per chunk.
   const int nk = (Ki + KC - 1) / KC;
   T ra[PF][AL], rb[PF][BL];
-#pragma unroll
-  for (int u = 0; u < PF; ++u) gload(ra[u], rb[u], u * KC);
-  sstore(ra[0], rb[0], 0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; kc += PF) {
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int c = kc + u;
-      gload(ra[u], rb[u], (c + PF) * KC);
-      if (c < nk) compute(c & 1);
-      if (c + 1 < nk) sstore(ra[(u + 1) % PF], rb[(u + 1) % PF], (c + 1) & 1);
+  if constexpr (PF == 2) {
+    // Two register sets keep two K chunks in flight: while LDS buffer c is
+    // consumed, chunk k+1 travels into the other register set and chunk k+2
+    // is requested.  Loads inside the steady-state loop are unconditional (a
+    // chunk past the end reads zeros from outside the buffer range without
+    // touching memory), so the outstanding-load count is the same on every
+    // path and each store waits only for its own chunk.  One barrier per
+    // chunk; the tail (one or two chunks) is peeled.
+    gload(ra[0], rb[0], 0);
+    gload(ra[1], rb[1], KC);
+    sstore(ra[0], rb[0], 0);
+    __syncthreads();
+    int kc = 0;
+    for (; kc + 2 < nk; kc += 2) {
+      gload(ra[0], rb[0], (kc + 2) * KC);
+      compute(0);
+      sstore(ra[1], rb[1], 1);
       __syncthreads();
+      gload(ra[1], rb[1], (kc + 3) * KC);
+      compute(1);
+      sstore(ra[0], rb[0], 0);
+      __syncthreads();
+    }
+    compute(0);  // buffer 0 holds chunk kc, set 1 chunk kc + 1
+    if (kc + 1 < nk) {
+      sstore(ra[1], rb[1], 1);
+      __syncthreads();
+      compute(1);
+    }
+  } else {
+    // PF register sets keep PF K chunks in flight.  At step c the LDS buffer
+    // c mod 2 holds chunk c, the sets hold chunks c+1 .. c+PF-1, and the set
+    // that held chunk c (already stored) requests chunk c+PF.
+#pragma unroll
+    for (int u = 0; u < PF; ++u) gload(ra[u], rb[u], u * KC);
+    sstore(ra[0], rb[0], 0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; kc += PF) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int c = kc + u;
+        gload(ra[u], rb[u], (c + PF) * KC);
+        if (c < nk) compute(c & 1);
+        if (c + 1 < nk) sstore(ra[(u + 1) % PF], rb[(u + 1) % PF], (c + 1) & 1);
+        __syncthreads();
+      }
     }
   }
 
   // acc[.][i][j][r] holds C[m, q] with m = wm0 + 16 i + (lane mod 16),
   // q = wq0 + 16 j + (lane / 16) + 4 r
   const long cbase = b * g.sC;
+  epilogue_tile<T>(g.epi, [&](auto&& f) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    const int m = m0 + wm0 + i * 16 + lr;
-    if (m >= Mi) continue;
+    for (int i = 0; i < FM; ++i) {
+      const int m = m0 + wm0 + i * 16 + lr;
+      if (m >= Mi) continue;
 #pragma unroll
-    for (int j = 0; j < FQ; ++j)
+      for (int j = 0; j < FQ; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + wq0 + j * 16 + lk + 4 * r;
-        if (q >= Qi) continue;
-        const long e = cbase + m + g.ldc * (long)q;
-        if constexpr (CPLX)
-          epilogue_store<T>(g.epi, e, cdouble{acc[0][i][j][r], acc[1][i][j][r]});
-        else
-          epilogue_store<T>(g.epi, e, acc[0][i][j][r]);
-      }
-  }
+        for (int r = 0; r < 4; ++r) {
+          const int q = q0 + wq0 + j * 16 + lk + 4 * r;
+          if (q >= Qi) continue;
+          const long e = cbase + m + g.ldc * (long)q;
+          if constexpr (CPLX)
+            f(e, cdouble{acc[0][i][j][r], acc[1][i][j][r]});
+          else
+            f(e, acc[0][i][j][r]);
+        }
+    }
+  });
 }
 
 template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF>
@@ -557,19 +599,22 @@ struct GemmArgsLP {
   GemmArgs g;      // shapes, strides, epilogue (out0 is float* when out32)
 };
 
-template <bool OUT32>
-__device__ __forceinline__ void lp_store(const Epilogue& ep, long e, float y) {
-  if constexpr (OUT32)
-    static_cast<float*>(ep.out0)[e] = y;
-  else
-    epilogue_store<double>(ep, e, (double)y);
-}
-template <bool OUT32>
-__device__ __forceinline__ void lp_store_c(const Epilogue& ep, long e, float yr, float yi) {
-  if constexpr (OUT32)
-    static_cast<cfloat*>(ep.out0)[e] = cfloat{yr, yi};
-  else
-    epilogue_store<cdouble>(ep, e, cdouble{(double)yr, (double)yi});
+// Stores of the reduced-precision kernels: an FP32 intermediate tensor is
+// written as it is, the last mode goes through the FP64 epilogue.
+template <bool OUT32, bool CPLX, typename Elems>
+__device__ __forceinline__ void lp_store_tile(const Epilogue& ep, Elems&& elems) {
+  if constexpr (OUT32) {
+    if constexpr (CPLX)
+      elems([&](long e, float yr, float yi) { static_cast<cfloat*>(ep.out0)[e] = cfloat{yr, yi}; });
+    else
+      elems([&](long e, float y, float) { static_cast<float*>(ep.out0)[e] = y; });
+  } else if constexpr (CPLX) {
+    epilogue_tile<cdouble>(ep, [&](auto&& f) {
+      elems([&](long e, float yr, float yi) { f(e, cdouble{(double)yr, (double)yi}); });
+    });
+  } else {
+    epilogue_tile<double>(ep, [&](auto&& f) { elems([&](long e, float y, float) { f(e, (double)y); }); });
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -713,22 +758,21 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
   }
   // acc[i][j][r]: m = wm0 + 16 i + (lane mod 16), q = wq0 + 16 j + 4 (lane / 16) + r
   const long cbase = b * g.sC;
+  lp_store_tile<OUT32, CPLX>(g.epi, [&](auto&& f) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    const int m = m0 + wm0 + i * 16 + lr;
-    if (m >= Mi) continue;
+    for (int i = 0; i < FM; ++i) {
+      const int m = m0 + wm0 + i * 16 + lr;
+      if (m >= Mi) continue;
 #pragma unroll
-    for (int j = 0; j < FQ; ++j)
+      for (int j = 0; j < FQ; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + wq0 + j * 16 + 4 * lk + r;
-        if (q >= Qi) continue;
-        if constexpr (CPLX)
-          lp_store_c<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[0][i][j][r], acc[1][i][j][r]);
-        else
-          lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[0][i][j][r]);
-      }
-  }
+        for (int r = 0; r < 4; ++r) {
+          const int q = q0 + wq0 + j * 16 + 4 * lk + r;
+          if (q >= Qi) continue;
+          f(cbase + m + g.ldc * (long)q, acc[0][i][j][r], CPLX ? acc[NP - 1][i][j][r] : 0.0f);
+        }
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -894,19 +938,21 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs
     compute(1);
   }
   const long cbase = b * g.sC;
+  lp_store_tile<OUT32, false>(g.epi, [&](auto&& f) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i) {
-    const int m = m0 + wm0 + i * 16 + lr;
-    if (m >= Mi) continue;
+    for (int i = 0; i < FM; ++i) {
+      const int m = m0 + wm0 + i * 16 + lr;
+      if (m >= Mi) continue;
 #pragma unroll
-    for (int j = 0; j < FQ; ++j)
+      for (int j = 0; j < FQ; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + wq0 + j * 16 + 4 * lk + r;
-        if (q >= Qi) continue;
-        lp_store<OUT32>(g.epi, cbase + m + g.ldc * (long)q, acc[i][j][r]);
-      }
-  }
+        for (int r = 0; r < 4; ++r) {
+          const int q = q0 + wq0 + j * 16 + 4 * lk + r;
+          if (q >= Qi) continue;
+          f(cbase + m + g.ldc * (long)q, acc[i][j][r], 0.0f);
+        }
+    }
+  });
 }
 
 template <int PREC, typename TA, typename TB, bool OUT32, bool BK>
