@@ -27,6 +27,8 @@ METRIC = "DOF-steps/s + % of MFMA roofline, FP64 vs split-BF16 at stated rel. er
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 PEAK_BF16_TFLOPS = 2516.6  # MI355X dense BF16 MFMA
+PEAK_INT8_TOPS = 5000.0    # MI355X dense INT8 MFMA
+SLICE_PRODUCTS = 26        # digit products a_i b_j (i + j <= 6) per multiply-add of the exact-slice path
 PEAK_HBM_GBS = 8000.0
 
 
@@ -212,7 +214,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="adr128")
     ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "slice"],
                     help="contraction precision of the mu-mode products (state and phi stay FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -280,10 +282,11 @@ def main():
     Ms = [px.matrix_to_device(px.phi_setup(a, p.tau, ell)[ell], device=dev) for a in p.A]
     Vk = U0.clone()
     Wk = torch.empty_like(Vk)
-    ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64), 16),
+    prec_code = {"fp64": px.PREC_FP64, "fp32": px.PREC_FP32, "bf16x3": px.PREC_BF16X3,
+                 "slice": px.PREC_SLICED}[args.precision]
+    ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64, prec_code), 16),
                      dtype=torch.uint8, device=dev)
     with torch.cuda.stream(stream):
-        prec_code = {"fp64": px.PREC_FP64, "fp32": px.PREC_FP32, "bf16x3": px.PREC_BF16X3}[args.precision]
         for _ in range(3):
             px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
         k0 = torch.cuda.Event(enable_timing=True)
@@ -309,6 +312,16 @@ def main():
             "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(args.workload),
         }
+    elif args.precision == "slice":
+        # one mode of tucker_apply: digits of M (n^2) and of the tensor (read 8 B, write
+        # 6 B per element), then the int8 GEMM (read 6 B, write 8 B per element)
+        alg_bytes = 28 * p.N
+        hw_tops = SLICE_PRODUCTS * flops_per_launch / avg_launch_s / 1e12
+        roofline = {"kernel": "k_slice_* + k_sliced_gemm (exact-slice mu-mode product, int8 MFMA)",
+                    "bound": "mfma", "achieved": round(hw_tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+                    "frac": round(hw_tops / PEAK_INT8_TOPS, 4), "traffic": None,
+                    "algorithmic_tflops_fp64_equivalent": round(achieved_tf, 3),
+                    "hardware_op_multiplier": SLICE_PRODUCTS}
     else:
         # a reduced-precision Tucker reads FP64, keeps FP32 intermediates, writes FP64:
         # d modes move (8 + 4) + (4 + 4) (d - 2) + (4 + 8) bytes per element in total
@@ -351,7 +364,8 @@ def main():
         "vs_baseline": None,
         "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
                  ("c64 (state c128)" if p.is_complex else
-                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)"}[args.precision]),
+                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
+                   "slice": "int8 digits x6/int32 acc (state f64)"}[args.precision]),
         "data": "synthetic",
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
                    "precision": args.precision, "graph": True},

@@ -50,6 +50,13 @@ extern "C" {
 #define EXPINT_PREC_FP64    0
 #define EXPINT_PREC_FP32    1   /* operands rounded to FP32, FP32 MFMA */
 #define EXPINT_PREC_BF16X3  2   /* x = hi + lo (bf16, RNE); hi*hi + hi*lo + lo*hi, FP32 accumulate */
+#define EXPINT_PREC_SLICED  3   /* exact-slice: every operand fibre (a row of M, a fibre of the
+                                   tensor along the contracted mode) as 6 balanced base-128 int8
+                                   digits under one power-of-two exponent; the 26 digit products
+                                   a_i b_j with i + j <= 6 summed exactly in int32 on int8 MFMA
+                                   and combined in FP64.  Error of one contraction at most
+                                   2^-41 (max|v| sum|m| + max|m| sum|v|) + n 2^-44.6 max|m| max|v|
+                                   over the contracted fibres; FP64 between modes */
 
 /* time-stepping schemes (paper section 2; tensor forms in section 3.2) */
 #define EXPINT_LAWSON_EULER  0  /* eq. lawsoneulertensor */
@@ -111,10 +118,12 @@ int phi_setup_z(int n, const double* A, int lda, double tau, int ell_max,
  *   W          device output tensor
  *   alpha,beta real scalars; beta == 0 means W is not read
  *   dtype      EXPINT_F64 or EXPINT_C128
- *   precision  EXPINT_PREC_FP64, or (real data only) EXPINT_PREC_FP32 /
- *              EXPINT_PREC_BF16X3: operands rounded to FP32 or split into two
- *              bf16 parts, FP32 accumulation, FP32 intermediates between
- *              modes, FP64 result
+ *   precision  EXPINT_PREC_FP64; EXPINT_PREC_FP32 (real or complex data):
+ *              operands rounded to FP32, FP32 accumulation; (real data only)
+ *              EXPINT_PREC_BF16X3: operands split into two bf16 parts, FP32
+ *              accumulation -- both keep FP32 intermediates between modes and
+ *              return FP64; EXPINT_PREC_SLICED (real data only, n[mu] <=
+ *              65535): exact-slice digits on int8 MFMA, FP64 intermediates
  *   ws         device workspace of at least tucker_workspace_size() bytes
  *              (may be NULL when that size is 0)
  *   stream     hipStream_t
@@ -125,8 +134,10 @@ int tucker_apply(int d, const int* n, const void* const* M, const void* V, void*
                  double alpha, double beta, int dtype, int precision,
                  void* ws, size_t ws_bytes, void* stream);
 
-/* tucker_workspace_size -- bytes of workspace tucker_apply needs. */
-int tucker_workspace_size(int d, const int* n, int dtype, size_t* bytes);
+/* tucker_workspace_size -- bytes of workspace tucker_apply needs for this
+ * shape, element type and precision (every M non-NULL; fewer modes need no
+ * more).  Errors: EINVAL for a bad shape, dtype or precision. */
+int tucker_workspace_size(int d, const int* n, int dtype, int precision, size_t* bytes);
 
 /* ------------------------------------------------------------------------ */
 /* plans and time stepping                                                   */
@@ -145,8 +156,9 @@ typedef struct expint_problem {
   double g_param2;       /* alpha of EXPINT_G_ADR_PAPER */
   int dtype;             /* EXPINT_F64 or EXPINT_C128 */
   int precision;         /* contraction precision of the Tucker operators (EXPINT_PREC_*;
-                            reduced precision for real data only); K u, g and the
-                            stage combination stay FP64 */
+                            complex data: FP64 or FP32 only); K u, g and the stage
+                            combination stay FP64.  EXPINT_PREC_SLICED keeps int8
+                            digits of every phi in the plan */
 } expint_problem;
 
 /*

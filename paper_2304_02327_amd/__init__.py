@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     PREC_BF16X3,
     PREC_FP32,
     PREC_FP64,
+    PREC_SLICED,
     SCHEMES,
     ExpintError,
     Plan,

@@ -24,10 +24,10 @@ LIB_PATH = os.path.join(_HERE, "libexpint.so")
 # status codes, dtypes, precisions, schemes, nonlinearities (include/expint.h)
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, C128 = 0, 1
-PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_SLICED = 0, 1, 2, 3
 SCHEMES = {"lawson_euler": 0, "lawson2b": 1, "exp_euler": 2, "etd2rk": 3}
 NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3, "adr_paper": 4}
-PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "slice": PREC_SLICED}
 
 
 class ExpintError(RuntimeError):
@@ -50,7 +50,7 @@ def _load():
     lib.phi_setup_z.argtypes = [c_int, dp, c_int, c_double, c_int, dp, c_int]
     lib.tucker_apply.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
                                  c_double, c_double, c_int, c_int, c_void_p, c_size_t, c_void_p]
-    lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, ctypes.POINTER(c_size_t)]
+    lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_size_t)]
     lib.expint_plan_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_void_p]
     lib.expint_plan_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
     lib.expint_plan_set_phi.argtypes = [c_void_p, c_int, c_int, dp]
@@ -183,17 +183,23 @@ def _check_device_tensor(t, name):
 # tucker_apply
 # ---------------------------------------------------------------------------
 
-def tucker_workspace_size(n: Sequence[int], dtype: int = F64) -> int:
+def _precision_code(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def tucker_workspace_size(n: Sequence[int], dtype: int = F64, precision=PREC_FP64) -> int:
     d = len(n)
     arr = (ctypes.c_int * d)(*n)
     out = ctypes.c_size_t(0)
-    _check(lib.tucker_workspace_size(d, arr, dtype, ctypes.byref(out)))
+    _check(lib.tucker_workspace_size(d, arr, dtype, _precision_code(precision), ctypes.byref(out)))
     return out.value
 
 
 def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
-                 precision: int = PREC_FP64, ws=None, stream=None):
-    """W = alpha * (V x_1 M_1 ... x_d M_d) + beta * W on the device (M_mu = None: identity)."""
+                 precision=PREC_FP64, ws=None, stream=None):
+    """W = alpha * (V x_1 M_1 ... x_d M_d) + beta * W on the device (M_mu = None: identity).
+    precision: a PREC_* code or one of "fp64", "fp32", "bf16x3", "slice"."""
+    precision = _precision_code(precision)
     import torch
     _check_device_tensor(V, "V")
     _check_device_tensor(W, "W")
@@ -211,7 +217,7 @@ def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
             if tuple(M.shape) != (n[mu], n[mu]) or M.dtype != V.dtype:
                 raise ValueError(f"M[{mu}] must be {n[mu]}x{n[mu]} of {V.dtype}")
             ptrs[mu] = M.data_ptr()
-    need = tucker_workspace_size(n, dt)
+    need = tucker_workspace_size(n, dt, precision)
     if ws is None and need > 0:
         ws = torch.empty(need, dtype=torch.uint8, device=V.device)
     ws_ptr = ws.data_ptr() if ws is not None else None

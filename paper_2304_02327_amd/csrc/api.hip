@@ -1,9 +1,11 @@
 // C ABI: argument validation, plans and the per-step kernel sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -61,8 +63,39 @@ void mode_view(int d, const int* n, int mu, long* s, long* r) {
 // With a reduced contraction precision the inner modes keep FP32
 // intermediates in the ping-pong buffers (half the bytes of FP64) and the
 // last mode returns to FP64 through its epilogue.
+// Exact-slice chain: per mode, the digits of the current tensor along that
+// mode go to dig_ws, and the int8 product writes the FP64 result to t0 (the
+// slice kernel has consumed t0 before the product overwrites it).
+int tucker_chain_sliced(int d, const int* n, const void* const* M, const void* const* Mdig, const void* V,
+                        void* t0, void* dig_ws, const Epilogue& last, void* stream) {
+  int lastmu = -1;
+  for (int mu = 0; mu < d; ++mu)
+    if (M[mu]) lastmu = mu;
+  const void* src = V;
+  for (int mu = 0; mu < d; ++mu) {
+    if (!M[mu]) continue;
+    long s, r;
+    mode_view(d, n, mu, &s, &r);
+    TRY(launch_slice(static_cast<const double*>(src), s, n[mu], r, mu == 0, dig_ws, stream));
+    if (mu == lastmu) {
+      TRY(launch_sliced_mode_product(s, n[mu], r, mu == 0, Mdig[mu], dig_ws, last, stream));
+    } else {
+      Epilogue e;
+      e.op = EPI_AXPBY;
+      e.alpha = 1.0;
+      e.beta = 0.0;
+      e.out0 = t0;
+      TRY(launch_sliced_mode_product(s, n[mu], r, mu == 0, Mdig[mu], dig_ws, e, stream));
+      src = t0;
+    }
+  }
+  return EXPINT_OK;
+}
+
 int tucker_chain(int dtype, int precision, int d, const int* n, const void* const* M, const void* V,
-                 void* t0, void* t1, const Epilogue& last, void* stream) {
+                 void* t0, void* t1, const Epilogue& last, void* stream, const void* const* Mdig = nullptr,
+                 void* dig_ws = nullptr) {
+  if (precision == EXPINT_PREC_SLICED) return tucker_chain_sliced(d, n, M, Mdig, V, t0, dig_ws, last, stream);
   int lastmu = -1;
   for (int mu = 0; mu < d; ++mu)
     if (M[mu]) lastmu = mu;
@@ -98,8 +131,16 @@ int tucker_chain(int dtype, int precision, int d, const int* n, const void* cons
   return EXPINT_OK;
 }
 
+// Bytes of the digit buffer of a sliced chain: the largest per-mode tensor digits.
+size_t sliced_tensor_digits_bytes(int d, const int* n, long N) {
+  size_t b = 0;
+  for (int mu = 0; mu < d; ++mu) b = std::max(b, slice_digits_bytes(N / n[mu], n[mu]));
+  return b;
+}
+
 bool valid_precision(int precision) {
-  return precision == EXPINT_PREC_FP64 || precision == EXPINT_PREC_FP32 || precision == EXPINT_PREC_BF16X3;
+  return precision == EXPINT_PREC_FP64 || precision == EXPINT_PREC_FP32 || precision == EXPINT_PREC_BF16X3 ||
+         precision == EXPINT_PREC_SLICED;
 }
 
 int count_modes(int d, const void* const* M) {
@@ -151,13 +192,32 @@ static int validate_shape(int d, const int* n, long* N) {
   return EXPINT_OK;
 }
 
-extern "C" int tucker_workspace_size(int d, const int* n, int dtype, size_t* bytes) {
+// Workspace layout of tucker_apply: FP64 / FP32 / BF16X3 use up to two
+// ping-pong tensors of N elements; the exact-slice chain uses one FP64 tensor,
+// the digit buffer of the largest mode and the digits of every M.
+static int tucker_ws_layout(int d, const int* n, long N, int dtype, int precision, int modes, size_t* tensors,
+                            size_t* digits, size_t* mdigits) {
+  *tensors = *digits = *mdigits = 0;
+  if (precision == EXPINT_PREC_SLICED) {
+    *tensors = modes > 1 ? ((size_t)N * 8 + 255) / 256 * 256 : 0;
+    *digits = sliced_tensor_digits_bytes(d, n, N);
+    for (int mu = 0; mu < d; ++mu) *mdigits += slice_digits_bytes(n[mu], n[mu]);
+    return EXPINT_OK;
+  }
+  const int bufs = modes - 1 < 2 ? modes - 1 : 2;
+  *tensors = (size_t)bufs * (size_t)N * elem_size(dtype);
+  return EXPINT_OK;
+}
+
+extern "C" int tucker_workspace_size(int d, const int* n, int dtype, int precision, size_t* bytes) {
   long N;
   TRY(validate_shape(d, n, &N));
   if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
+  if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", precision);
   if (!bytes) return set_error(EXPINT_EINVAL, "bytes is NULL");
-  const int bufs = d - 1 < 2 ? d - 1 : 2;
-  *bytes = (size_t)bufs * (size_t)N * elem_size(dtype);
+  size_t t, g, m;
+  TRY(tucker_ws_layout(d, n, N, dtype, precision, d, &t, &g, &m));
+  *bytes = t + g + m;
   return EXPINT_OK;
 }
 
@@ -168,7 +228,7 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   TRY(validate_shape(d, n, &N));
   if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
   if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "tucker_apply: unknown precision %d", precision);
-  if (precision == EXPINT_PREC_BF16X3 && dtype != EXPINT_F64)
+  if ((precision == EXPINT_PREC_BF16X3 || precision == EXPINT_PREC_SLICED) && dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "tucker_apply: complex data supports FP64 or FP32 (complex64) contraction");
   if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
   if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
@@ -178,22 +238,32 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
     if (M[mu] && !aligned16(M[mu])) return set_error(EXPINT_EINVAL, "tucker_apply: M[%d] not 16-byte aligned", mu);
   const int modes = count_modes(d, M);
   if (modes == 0) return set_error(EXPINT_EINVAL, "tucker_apply: every M[mu] is NULL (nothing to apply)");
-  size_t need = 0;
-  {
-    const int bufs = modes - 1 < 2 ? modes - 1 : 2;
-    need = (size_t)bufs * (size_t)N * elem_size(dtype);
-  }
+  size_t tens, digs, mdigs;
+  TRY(tucker_ws_layout(d, n, N, dtype, precision, modes, &tens, &digs, &mdigs));
+  const size_t need = tens + digs + mdigs;
   if (ws_bytes < need || (need > 0 && !ws))
     return set_error(EXPINT_EINVAL, "tucker_apply: workspace of %zu bytes needed, %zu given", need, ws_bytes);
   if (need > 0 && !aligned16(ws)) return set_error(EXPINT_EINVAL, "tucker_apply: workspace not 16-byte aligned");
   char* w = static_cast<char*>(ws);
-  void* t0 = need ? w : nullptr;
-  void* t1 = need ? w + (size_t)N * elem_size(dtype) : nullptr;
   Epilogue last;
   last.op = EPI_AXPBY;
   last.alpha = alpha;
   last.beta = beta;
   last.out0 = W;
+  if (precision == EXPINT_PREC_SLICED) {
+    // digits of each M (rows along its columns), then the chain
+    const void* Md[4] = {nullptr, nullptr, nullptr, nullptr};
+    char* mp = w + tens + digs;
+    for (int mu = 0; mu < d; ++mu) {
+      if (!M[mu]) continue;
+      TRY(launch_slice(static_cast<const double*>(M[mu]), n[mu], n[mu], 1, false, mp, stream));
+      Md[mu] = mp;
+      mp += slice_digits_bytes(n[mu], n[mu]);
+    }
+    return tucker_chain(dtype, precision, d, n, M, V, tens ? w : nullptr, nullptr, last, stream, Md, w + tens);
+  }
+  void* t0 = tens ? w : nullptr;
+  void* t1 = tens ? w + (size_t)N * elem_size(dtype) : nullptr;
   return tucker_chain(dtype, precision, d, n, M, V, t0, t1, last, stream);
 }
 
@@ -211,6 +281,7 @@ struct expint_plan {
   int ell_lo = 0, ell_hi = 0;        // phi indices the scheme uses
   void* phi[4][3] = {};              // device phi_l(tau A_mu); shared between equal directions
   bool phi_owner[4][3] = {};
+  void* phidig[4][3] = {};           // exact-slice digits of phi (EXPINT_PREC_SLICED); always owned
   bool use_stencil = false;
   Stencil stencil;                   // device coefficient arrays when use_stencil
   void* denseA[4] = {};              // device A_mu for the dense K u path
@@ -254,6 +325,8 @@ void free_plan_memory(expint_plan* p) {
   for (int mu = 0; mu < 4; ++mu) {
     for (int l = 0; l < 3; ++l)
       if (p->phi_owner[mu][l] && p->phi[mu][l]) (void)hipFree(p->phi[mu][l]);
+    for (int l = 0; l < 3; ++l)
+      if (p->phidig[mu][l]) (void)hipFree(p->phidig[mu][l]);
     if (p->stencil.coef[mu]) (void)hipFree(const_cast<void*>(p->stencil.coef[mu]));
     if (p->denseA[mu]) (void)hipFree(p->denseA[mu]);
   }
@@ -300,6 +373,26 @@ int workspace_elems(const expint_plan* p, long* elems) {
   return EXPINT_OK;
 }
 
+// extra bytes after the scheme's tensors: the digit buffer of the exact-slice chain
+size_t workspace_extra_bytes(const expint_plan* p) {
+  if (p->precision != EXPINT_PREC_SLICED) return 0;
+  return 256 + sliced_tensor_digits_bytes(p->d, p->n, p->N);  // 256: room to align the digit buffer
+}
+
+// digits of phi_ell(tau A_mu) for the exact-slice contraction (synchronous)
+int slice_phi(expint_plan* p, int mu, int ell) {
+  const int n = p->n[mu];
+  if (!p->phidig[mu][ell]) {
+    void* dptr = nullptr;
+    if (hipMalloc(&dptr, slice_digits_bytes(n, n)) != hipSuccess)
+      return set_error(EXPINT_ENOMEM, "device allocation for phi digits failed");
+    p->phidig[mu][ell] = dptr;
+  }
+  TRY(launch_slice(static_cast<const double*>(p->phi[mu][ell]), n, n, 1, false, p->phidig[mu][ell], nullptr));
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  return EXPINT_OK;
+}
+
 // stage input W = tau (K U + g(U))
 int stage_input(expint_plan* p, const void* U, void* W, hipStream_t s) {
   if (p->use_stencil)
@@ -338,6 +431,13 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
   const void* P0[4] = {p->phi[0][0], p->phi[1][0], p->phi[2][0], p->phi[3][0]};
   const void* P1[4] = {p->phi[0][1], p->phi[1][1], p->phi[2][1], p->phi[3][1]};
   const void* P2[4] = {p->phi[0][2], p->phi[1][2], p->phi[2][2], p->phi[3][2]};
+  const void* D0[4] = {p->phidig[0][0], p->phidig[1][0], p->phidig[2][0], p->phidig[3][0]};
+  const void* D1[4] = {p->phidig[0][1], p->phidig[1][1], p->phidig[2][1], p->phidig[3][1]};
+  const void* D2[4] = {p->phidig[0][2], p->phidig[1][2], p->phidig[2][2], p->phidig[3][2]};
+  long elems;
+  TRY(workspace_elems(p, &elems));
+  // exact-slice digit buffer, 256-byte aligned after the scheme's tensors
+  void* DG = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(base + (size_t)elems * es) + 255) & ~uintptr_t(255));
   const double split2 = std::ldexp(1.0, p->d - 1);  // (2!)^{d-1}
   switch (p->scheme) {
     case EXPINT_LAWSON_EULER: {
@@ -346,7 +446,7 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
       Epilogue e;
       e.op = EPI_AXPBY;
       e.out0 = U;
-      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e, s, D0, DG);
     }
     case EXPINT_LAWSON2B: {
       // U_n2 = (U_n + tau G_n) x e^{tau A};  U_{n+1} = (U_n + tau/2 G_n) x e^{tau A} + tau/2 G(U_n2)
@@ -354,7 +454,7 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
       Epilogue e1;
       e1.op = EPI_AXPBY;
       e1.out0 = Y;
-      TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e1, s));
+      TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P0, W, T0, T1, e1, s, D0, DG));
       Epilogue e2;
       e2.op = EPI_LAWSON2B_2;
       e2.out0 = U;
@@ -363,7 +463,7 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e2.g = p->nonlin;
       e2.gparam = p->gparam;
       e2.gt = p->gt;
-      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, X, T0, T1, e2, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P0, X, T0, T1, e2, s, D0, DG);
     }
     case EXPINT_EXP_EULER: {
       // U_{n+1} = U_n + (tau (K U_n + G_n)) x_mu phi_1(tau A_mu)   ((1!)^{d-1} = 1)
@@ -372,7 +472,7 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
       e.op = EPI_EXP_EULER;
       e.out0 = U;
       e.in1 = U;
-      return tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e, s, D1, DG);
     }
     case EXPINT_ETD2RK: {
       // U_n2 = U_n + (tau (K U_n + G_n)) x phi_1;  W_2 = tau (G(U_n2) - G_n)
@@ -390,17 +490,17 @@ int enqueue_step_body(expint_plan* p, void* U, void* ws, hipStream_t s) {
       if (count_modes(p->d, P1) == 1) {
         // a single mode reads W while its epilogue writes W_2: keep them apart
         e1.out1 = T1;
-        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, nullptr, e1, s));
+        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, nullptr, e1, s, D1, DG));
         W = T1;
       } else {
-        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e1, s));
+        TRY(tucker_chain(p->dtype, p->precision, p->d, p->n, P1, W, T0, T1, e1, s, D1, DG));
       }
       Epilogue e2;
       e2.op = EPI_ETD2RK_2;
       e2.out0 = U;
       e2.in1 = X;
       e2.c = split2;
-      return tucker_chain(p->dtype, p->precision, p->d, p->n, P2, W, T0, T1, e2, s);
+      return tucker_chain(p->dtype, p->precision, p->d, p->n, P2, W, T0, T1, e2, s, D2, DG);
     }
   }
   return set_error(EXPINT_EINVAL, "unknown scheme");
@@ -425,7 +525,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)
     return set_error(EXPINT_EINVAL, "unknown dtype %d", prob->dtype);
   if (!valid_precision(prob->precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", prob->precision);
-  if (prob->precision == EXPINT_PREC_BF16X3 && prob->dtype != EXPINT_F64)
+  if ((prob->precision == EXPINT_PREC_BF16X3 || prob->precision == EXPINT_PREC_SLICED) && prob->dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "complex data supports FP64 or FP32 (complex64) contraction");
   if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
   const bool cplx = prob->dtype == EXPINT_C128;
@@ -499,6 +599,11 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
         rc = set_error(EXPINT_EHIP, "copy of phi to the device failed");
     }
   }
+
+  // exact-slice digits of every phi the scheme uses
+  if (rc == EXPINT_OK && p->precision == EXPINT_PREC_SLICED)
+    for (int mu = 0; mu < p->d && rc == EXPINT_OK; ++mu)
+      for (int l = lo; l <= hi && rc == EXPINT_OK; ++l) rc = slice_phi(p, mu, l);
 
   // operator data for K u: stencil if every A_mu is (periodic) tridiagonal, else dense
   if (rc == EXPINT_OK && (p->scheme == EXPINT_EXP_EULER || p->scheme == EXPINT_ETD2RK)) {
@@ -592,7 +697,7 @@ extern "C" int expint_plan_workspace_size(const expint_plan* p, size_t* bytes) {
   if (!p || !bytes) return set_error(EXPINT_EINVAL, "NULL plan or output");
   long elems;
   TRY(workspace_elems(p, &elems));
-  *bytes = (size_t)elems * elem_size(p->dtype);
+  *bytes = (size_t)elems * elem_size(p->dtype) + workspace_extra_bytes(p);
   return EXPINT_OK;
 }
 
@@ -615,6 +720,7 @@ extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double
     }
   }
   HIP_TRY(hipMemcpy(p->phi[mu][ell], host_phi, bytes, hipMemcpyHostToDevice));
+  if (p->precision == EXPINT_PREC_SLICED) TRY(slice_phi(p, mu, ell));
   return EXPINT_OK;
 }
 

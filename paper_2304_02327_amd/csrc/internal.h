@@ -71,6 +71,22 @@ long gemm_desc_tiles(const void* desc);
 int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
                         void* stream);
 
+// Exact-slice contraction (EXPINT_PREC_SLICED): each operand fibre is cut
+// into kSliceDigits balanced base-128 digits under one power-of-two exponent
+// and the digit products run exactly on int8 MFMA.  A digit buffer holds the
+// planes of `rows` fibres padded to slice_kpad(n) followed by their exponents.
+constexpr int kSliceDigits = 6;
+int slice_kpad(int n);
+size_t slice_digits_bytes(long rows, int n);
+// digits of the fibres along the middle index of V viewed as (s, n, r);
+// contiguous == true requires s == 1 (mode 1)
+int launch_slice(const double* V, long s, int n, long r, bool contiguous, void* out, void* stream);
+// mu-mode product from digit buffers: Mdig holds the n rows of M (launch_slice
+// of M viewed as (n, n, 1)), Vdig the fibres of V; mode1 selects the roles of
+// mode 1 (contiguous V fibres) or of the modes >= 2
+int launch_sliced_mode_product(long s, int n, long r, bool mode1, const void* Mdig, const void* Vdig,
+                               const Epilogue& epi, void* stream);
+
 // Reduced-precision contraction (EXPINT_PREC_FP32 / EXPINT_PREC_BF16X3; complex
 // data FP32 only) of a mu-mode product: V is FP32 (complex64) when v32, else
 // FP64 (complex128), M is FP64 / complex128; with out32 the result is stored

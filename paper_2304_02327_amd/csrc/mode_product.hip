@@ -26,6 +26,7 @@
 
 #include "device_common.h"
 #include "internal.h"
+#include "tile_common.h"
 
 namespace expint {
 namespace {
@@ -44,83 +45,12 @@ struct GemmArgs {
   Epilogue epi;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tile indices so that tiles that share an Aop block
-// (consecutive q-tiles) share that XCD's L2.
-__device__ __forceinline__ long xcd_remap(long L, long nt) {
-  constexpr long X = 8;
-  const long per = nt / X;
-  if (L >= per * X) return L;
-  return (L % X) * per + L / X;
-}
-
-template <typename T>
-__device__ __forceinline__ T ld(const void* p, long i) { return static_cast<const T*>(p)[i]; }
-
-// Applies the epilogue to the outputs a thread owns: visit(f) calls f(e, y)
-// for each of them.  The op and the nonlinearity are uniform per launch, so
-// they are dispatched once, outside the element loop: every path is a short
-// loop of its own and the code a launch runs stays compact.
-template <typename T, typename Visit>
-__device__ __forceinline__ void epilogue_tile(const Epilogue& ep, Visit&& visit) {
-  T* out0 = static_cast<T*>(ep.out0);
-  switch (ep.op) {
-    case EPI_AXPBY:
-      if (ep.beta != 0.0)
-        visit([&](long e, T y) { out0[e] = add(scale(y, ep.alpha), scale(out0[e], ep.beta)); });
-      else
-        visit([&](long e, T y) { out0[e] = scale(y, ep.alpha); });
-      break;
-    case EPI_EXP_EULER:
-      visit([&](long e, T y) { out0[e] = add(ld<T>(ep.in1, e), y); });
-      break;
-    case EPI_ETD2RK_1:
-      // U_n2 = U_n + Y and W_2 = tau (g(t_{n+1}, U_n2) - g(t_n, U_n))
-      dispatch_g(ep, T{}, [&](const auto& G) {
-        const auto g1 = G.at(ep.tau);
-        const auto g0 = G.at(0.0);
-        T* out1 = static_cast<T*>(ep.out1);
-        visit([&](long e, T y) {
-          const T u = ld<T>(ep.in1, e);
-          const T u2 = add(u, y);
-          out0[e] = u2;
-          out1[e] = scale(sub(g1(u2, e), g0(u, e)), ep.tau);
-        });
-      });
-      break;
-    case EPI_ETD2RK_2:
-      visit([&](long e, T y) { out0[e] = add(ld<T>(ep.in1, e), scale(y, ep.c)); });
-      break;
-    case EPI_LAWSON2B_2:  // U_{n+1} = Y + tau/2 g(t_{n+1}, U_n2)
-      dispatch_g(ep, T{}, [&](const auto& G) {
-        const auto g1 = G.at(2.0 * ep.c);
-        visit([&](long e, T y) { out0[e] = add(y, scale(g1(ld<T>(ep.in1, e), e), ep.c)); });
-      });
-      break;
-    case EPI_LINEAR:
-      visit([&](long e, T y) {
-        T v = scale(y, ep.alpha);
-        if (ep.in1) v = add(v, scale(ld<T>(ep.in1, e), ep.beta));
-        if (ep.in2) v = add(v, scale(ld<T>(ep.in2, e), ep.c));
-        out0[e] = v;
-      });
-      break;
-    default:
-      break;
-  }
-}
-
 // Buffer loads: a resource covers exactly one operand (matrix, slab or whole
 // tensor), so a read past its end returns zero in hardware.  A K index past
 // the end always lands past the end of the operand's range (the operands are
 // K-major beyond their last K row), and rows or columns past M or Q are sent
 // there explicitly through an out-of-range offset computed once per thread.
 // The per-chunk advance along K is a scalar offset.
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)bytes, 0x00020000);
-}
-
 template <typename T>
 __device__ __forceinline__ T buffer_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
 template <>

@@ -111,6 +111,29 @@ def test_tucker_workspace_size_and_validation():
     assert px.tucker_workspace_size([4, 5, 6], px.C128) == 2 * 120 * 16
     with pytest.raises(px.ExpintError):
         px.tucker_workspace_size([4, 0])
+    with pytest.raises(px.ExpintError):
+        px.tucker_workspace_size([4, 5], px.F64, 4)
+
+
+def _r256(b):
+    return (b + 255) // 256 * 256
+
+
+def test_sliced_workspace_layout():
+    """Exact-slice workspace: one FP64 tensor, the digit buffer of the largest
+    mode (6 int8 planes of fibres padded to 64, then int32 exponents) and the
+    digits of every M."""
+    n = [40, 41, 130]
+    N = 40 * 41 * 130
+
+    def digits(rows, k):
+        kp = (k + 63) // 64 * 64
+        return _r256(6 * rows * kp) + _r256(4 * rows)
+
+    expect = _r256(8 * N) + max(digits(N // k, k) for k in n) + sum(digits(k, k) for k in n)
+    assert px.tucker_workspace_size(n, px.F64, px.PREC_SLICED) == expect
+    assert px.tucker_workspace_size(n, px.F64, "slice") == expect
+    assert px.tucker_workspace_size([9], px.F64, "slice") == digits(1, 9) + digits(9, 9)
     # invalid calls return before any device work
     n = (ctypes.c_int * 2)(4, 5)
     ptrs = (ctypes.c_void_p * 2)(None, None)
