@@ -195,6 +195,12 @@ int expint_step(expint_plan* plan, void* U, double t, void* ws, void* stream);
  * expint_run -- nsteps >= 0 steps from t0.  use_graph != 0 captures one step
  * into a HIP graph (once per plan / U / ws / stream combination) and replays
  * it nsteps times; use_graph == 0 enqueues the kernels directly.
+ * A small two-dimensional FP64 problem (real data, n[0], n[1] <= 64, FP64
+ * contraction, autonomous g) instead runs all nsteps steps in one fused
+ * launch of a single workgroup with the state in LDS (expint_step then
+ * launches it for one step); use_graph does not change the result.  Setting
+ * the environment variable EXPINT_SMALL_FUSED=0 before expint_plan_create
+ * keeps such a plan on the general kernel sequence.
  */
 int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
                void* ws, void* stream);

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -290,6 +291,7 @@ struct expint_plan {
   GridTime gt;
   double* d_clock = nullptr;
   bool timedep = false;
+  bool small = false;                // whole runs in one fused launch (small 2-D FP64 problems)
   // cached graph of one step
   hipGraphExec_t gexec = nullptr;
   const void* g_U = nullptr;
@@ -689,6 +691,12 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
     delete p;
     return rc;
   }
+  {
+    const char* env = std::getenv("EXPINT_SMALL_FUSED");
+    const bool allowed = !(env && env[0] == '0');
+    p->small = allowed && small2d_fits(p->d, p->n) && p->dtype == EXPINT_F64 &&
+               p->precision == EXPINT_PREC_FP64 && !p->timedep;
+  }
   *out = p;
   return EXPINT_OK;
 }
@@ -724,9 +732,31 @@ extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double
   return EXPINT_OK;
 }
 
+// all steps of a small 2-D problem in one fused launch
+static int run_small(expint_plan* p, void* U, int nsteps, void* stream) {
+  SmallArgs a;
+  a.U = static_cast<double*>(U);
+  for (int mu = 0; mu < 2; ++mu) {
+    for (int l = 0; l < 3; ++l) a.M[mu][l] = static_cast<const double*>(p->phi[mu][l]);
+    a.stc[mu] = static_cast<const double*>(p->stencil.coef[mu]);
+    a.periodic[mu] = p->stencil.periodic[mu];
+    a.A[mu] = static_cast<const double*>(p->denseA[mu]);
+  }
+  a.stencil = p->use_stencil ? 1 : 0;
+  a.n1 = p->n[0];
+  a.n2 = p->n[1];
+  a.tau = p->tau;
+  a.gparam = p->gparam;
+  a.scheme = p->scheme;
+  a.g = p->nonlin;
+  a.nsteps = nsteps;
+  return launch_small2d(a, stream);
+}
+
 extern "C" int expint_step(expint_plan* p, void* U, double t, void* ws, void* stream) {
   TRY(validate_step_args(p, U, ws));
   if (!std::isfinite(t)) return set_error(EXPINT_EINVAL, "t is not finite");
+  if (p->small) return run_small(p, U, 1, stream);
   if (p->timedep) TRY(launch_clock_set(p->d_clock, t, stream));
   return enqueue_step(p, U, ws, static_cast<hipStream_t>(stream));
 }
@@ -737,6 +767,7 @@ extern "C" int expint_run(expint_plan* p, void* U, double t0, int nsteps, int us
   if (nsteps < 0) return set_error(EXPINT_EINVAL, "nsteps < 0");
   if (!std::isfinite(t0)) return set_error(EXPINT_EINVAL, "t0 is not finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->small) return run_small(p, U, nsteps, stream);
   // t_n = t0 + n tau for the steps below (the captured step advances n)
   if (p->timedep) TRY(launch_clock_set(p->d_clock, t0, s));
   if (!use_graph) {

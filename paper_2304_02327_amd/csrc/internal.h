@@ -71,6 +71,25 @@ long gemm_desc_tiles(const void* desc);
 int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
                         void* stream);
 
+// Fused time stepping of a small two-dimensional FP64 problem (n1, n2 <= 64):
+// one workgroup runs nsteps steps with the state in LDS.  M[mu][l] are the
+// device phi_l(tau A_mu) the scheme uses; K u comes from the stencil
+// coefficients (3 x n per direction, sub / diag / super) or the dense A_mu.
+struct SmallArgs {
+  double* U = nullptr;
+  const double* M[2][3] = {};
+  const double* stc[2] = {};
+  int periodic[2] = {0, 0};
+  const double* A[2] = {};
+  int stencil = 0;
+  int n1 = 1, n2 = 1;
+  double tau = 0.0, gparam = 0.0;
+  int scheme = 0, g = 0;
+  int nsteps = 0;
+};
+bool small2d_fits(int d, const int* n);
+int launch_small2d(const SmallArgs& a, void* stream);
+
 // Exact-slice contraction (EXPINT_PREC_SLICED): each operand fibre is cut
 // into kSliceDigits balanced base-128 digits under one power-of-two exponent
 // and the digit products run exactly on int8 MFMA.  A digit buffer holds the
