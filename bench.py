@@ -276,8 +276,103 @@ def main():
     if not torch.isfinite(U).all():
         raise SystemExit("non-finite state after the timed region")
 
-    # dominant kernel: the mu-mode product; time it alone with events on its stream,
-    # with the shapes and launch configuration of the step (the phi_1 Tucker)
+    if plan.fused:
+        # the whole timed run is one launch of the fused small-problem kernel: its
+        # duration is the event time of the timed region, its work the Tucker flops
+        # of every step; one workgroup can use at most one CU's share of the peak
+        flops_per_launch = tucker_flops_per_step(p) * args.steps
+        avg_launch_s = gpu_ms / 1e3
+        achieved_tf = flops_per_launch / avg_launch_s / 1e12
+        roofline = {
+            "kernel": "k_small2d (fused single-workgroup run, FP64 MFMA)",
+            "bound": "mfma",
+            "achieved": round(achieved_tf, 4),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 5),
+            "traffic": None,
+            "frac_of_one_cu": round(achieved_tf / (PEAK_FP64_TFLOPS / 256), 4),
+            "traffic_unit": "bytes per launch (state read once, written once)",
+            "algorithmic_bytes_per_launch": 2 * 8 * p.N,
+            "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "flops_per_launch": flops_per_launch,
+            "us_per_step": round(avg_launch_s * 1e6 / max(args.steps, 1), 3),
+        }
+    else:
+        roofline = tucker_roofline(args, p, px, dev, stream, U0)
+    step_tf = tucker_flops_per_step(p) * args.steps / (gpu_ms / 1e3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
+                 ("c64 (state c128)" if p.is_complex else
+                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
+                   "slice": "int8 digits x6/int32 acc (state f64)"}[args.precision]),
+        "data": "synthetic",
+        "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
+                   "precision": args.precision, "graph": True},
+        "wall_s_timed_region": wall,
+        "tucker_tflops_whole_step": round(step_tf, 3),
+        "roofline": roofline,
+    }
+
+    if args.workload in PAPER_RUNS and args.steps == p.steps:
+        # the whole integration to T = 1, against the paper's run of the same problem
+        _, _, paper_s, paper_err = PAPER_RUNS[args.workload]
+        exact = math.exp(1.0) * np.asarray(p.u0)  # the manufactured solution e^t u0 at t = 1
+        Uh = px.tensor_from_device(U)
+        err = float(np.abs(Uh - exact).max() / np.abs(exact).max())
+        paper_value = p.N * p.steps / paper_s
+        result["vs_baseline"] = value / paper_value
+        result["paper_run"] = {
+            "hardware": PAPER_HW, "seconds": paper_s, "steps": p.steps,
+            "dof_steps_per_s": paper_value, "rel_err_inf_printed": paper_err,
+        }
+        result["rel_err_inf_vs_exact_at_T"] = err
+        result["seconds_setup_plus_steps"] = setup_s + gpu_ms / 1e3
+        result["setup_s_phi_on_host_and_upload"] = setup_s
+    if args.precision != "fp64":
+        # error of the reduced-precision run against the FP64 path after the same steps
+        ref_plan = px.Plan(p.A, p.tau, p.scheme, p.g, **plan_kwargs(p))
+        Uref = U0.clone()
+        ref_plan.run(Uref, args.steps)
+        torch.cuda.synchronize()
+        d = (U - Uref).abs().max().item() / Uref.abs().max().item()
+        result["rel_err_vs_fp64"] = d
+        ref_plan.close()
+    if p.g == "cubic_nls":
+        # Lawson-Euler with a unitary e^{tau A}: sum|U_{n+1}|^2 = sum|U_n|^2 (1 + tau^2 |U_n|^4)
+        Um = U0.clone()
+        worst = 0.0
+        for _ in range(10):
+            prev = Um.clone()
+            plan.step(Um)
+            torch.cuda.synchronize()
+            a2 = prev.abs() ** 2
+            lhs = (Um.abs() ** 2).sum().item()
+            rhs = (a2 * (1 + p.tau ** 2 * a2 * a2)).sum().item()
+            worst = max(worst, abs(lhs - rhs) / rhs)
+        result["mass_identity_max_rel_residual_10_steps"] = worst
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(result))
+
+
+def tucker_roofline(args, p, px, dev, stream, U0):
+    """Roofline of the dominant kernel, the mu-mode product: tucker_apply with the
+    shapes and launch configuration of the step (the phi_1 Tucker), timed alone with
+    HIP events on the stream it is launched on."""
+    import torch
     ell = 1 if p.scheme in ("exp_euler", "etd2rk") else 0
     Ms = [px.matrix_to_device(px.phi_setup(a, p.tau, ell)[ell], device=dev) for a in p.A]
     Vk = U0.clone()
@@ -349,72 +444,7 @@ def main():
         "avg_launch_us": round(avg_launch_s * 1e6, 3),
         "flops_per_launch": flops_per_launch,
     })
-    step_tf = tucker_flops_per_step(p) * args.steps / (gpu_ms / 1e3) / 1e12
-
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "DOF-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
-                 ("c64 (state c128)" if p.is_complex else
-                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
-                   "slice": "int8 digits x6/int32 acc (state f64)"}[args.precision]),
-        "data": "synthetic",
-        "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
-                   "precision": args.precision, "graph": True},
-        "wall_s_timed_region": wall,
-        "tucker_tflops_whole_step": round(step_tf, 3),
-        "roofline": roofline,
-    }
-
-    if args.workload in PAPER_RUNS and args.steps == p.steps:
-        # the whole integration to T = 1, against the paper's run of the same problem
-        _, _, paper_s, paper_err = PAPER_RUNS[args.workload]
-        exact = math.exp(1.0) * np.asarray(p.u0)  # the manufactured solution e^t u0 at t = 1
-        Uh = px.tensor_from_device(U)
-        err = float(np.abs(Uh - exact).max() / np.abs(exact).max())
-        paper_value = p.N * p.steps / paper_s
-        result["vs_baseline"] = value / paper_value
-        result["paper_run"] = {
-            "hardware": PAPER_HW, "seconds": paper_s, "steps": p.steps,
-            "dof_steps_per_s": paper_value, "rel_err_inf_printed": paper_err,
-        }
-        result["rel_err_inf_vs_exact_at_T"] = err
-        result["seconds_setup_plus_steps"] = setup_s + gpu_ms / 1e3
-        result["setup_s_phi_on_host_and_upload"] = setup_s
-    if args.precision != "fp64":
-        # error of the reduced-precision run against the FP64 path after the same steps
-        ref_plan = px.Plan(p.A, p.tau, p.scheme, p.g, **plan_kwargs(p))
-        Uref = U0.clone()
-        ref_plan.run(Uref, args.steps)
-        torch.cuda.synchronize()
-        d = (U - Uref).abs().max().item() / Uref.abs().max().item()
-        result["rel_err_vs_fp64"] = d
-        ref_plan.close()
-    if p.g == "cubic_nls":
-        # Lawson-Euler with a unitary e^{tau A}: sum|U_{n+1}|^2 = sum|U_n|^2 (1 + tau^2 |U_n|^4)
-        Um = U0.clone()
-        worst = 0.0
-        for _ in range(10):
-            prev = Um.clone()
-            plan.step(Um)
-            torch.cuda.synchronize()
-            a2 = prev.abs() ** 2
-            lhs = (Um.abs() ** 2).sum().item()
-            rhs = (a2 * (1 + p.tau ** 2 * a2 * a2)).sum().item()
-            worst = max(worst, abs(lhs - rhs) / rhs)
-        result["mass_identity_max_rel_residual_10_steps"] = worst
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
-    plan.close()
-    print(json.dumps(result))
+    return roofline
 
 
 def cpu_baseline(p, plan, U0, budget_s):

@@ -205,6 +205,10 @@ int expint_step(expint_plan* plan, void* U, double t, void* ws, void* stream);
 int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
                void* ws, void* stream);
 
+/* expint_plan_is_fused -- *fused = 1 if the plan runs its steps in the fused
+ * small-problem launch described at expint_run, else 0.  Errors: EINVAL. */
+int expint_plan_is_fused(const expint_plan* plan, int* fused);
+
 /* expint_plan_destroy -- frees the plan's device memory and graph (NULL is a no-op).
  * The caller must make sure no enqueued work still uses the plan. */
 void expint_plan_destroy(expint_plan* plan);

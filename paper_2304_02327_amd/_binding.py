@@ -56,6 +56,7 @@ def _load():
     lib.expint_plan_set_phi.argtypes = [c_void_p, c_int, c_int, dp]
     lib.expint_step.argtypes = [c_void_p, c_void_p, c_double, c_void_p, c_void_p]
     lib.expint_run.argtypes = [c_void_p, c_void_p, c_double, c_int, c_int, c_void_p, c_void_p]
+    lib.expint_plan_is_fused.argtypes = [c_void_p, ctypes.POINTER(c_int)]
     lib.expint_plan_destroy.argtypes = [c_void_p]
     lib.expint_plan_destroy.restype = None
     lib.expint_riccati_plan_create.argtypes = [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_int),
@@ -77,7 +78,8 @@ lib = _load()
 EXPORTED_SYMBOLS = (
     "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
-    "expint_step", "expint_run", "expint_plan_destroy", "expint_last_error", "expint_version",
+    "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_destroy", "expint_last_error",
+    "expint_version",
     "expint_riccati_plan_create", "expint_batch_state_size", "expint_batch_workspace_size",
     "expint_batch_step", "expint_batch_run", "expint_batch_plan_destroy",
 )
@@ -271,6 +273,13 @@ class Plan:
         _check(lib.expint_plan_workspace_size(self._handle, ctypes.byref(size)))
         self.workspace_bytes = size.value
         self.ws = torch.empty(max(self.workspace_bytes, 16), dtype=torch.uint8, device=self.device)
+
+    @property
+    def fused(self) -> bool:
+        """True if runs go through the fused small-problem launch (one kernel for all steps)."""
+        out = ctypes.c_int(0)
+        _check(lib.expint_plan_is_fused(self._handle, ctypes.byref(out)))
+        return bool(out.value)
 
     def set_phi(self, mu: int, ell: int, M: np.ndarray):
         npdt = np.complex128 if self.dtype == C128 else np.float64

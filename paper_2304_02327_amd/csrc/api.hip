@@ -732,6 +732,12 @@ extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double
   return EXPINT_OK;
 }
 
+extern "C" int expint_plan_is_fused(const expint_plan* p, int* fused) {
+  if (!p || !fused) return set_error(EXPINT_EINVAL, "NULL plan or output");
+  *fused = p->small ? 1 : 0;
+  return EXPINT_OK;
+}
+
 // all steps of a small 2-D problem in one fused launch
 static int run_small(expint_plan* p, void* U, int nsteps, void* stream) {
   SmallArgs a;
