@@ -111,3 +111,55 @@ def run_problem(problem, steps: Optional[int] = None, phis=None, callback=None):
     """Integrate a ``workloads.Problem`` for ``steps`` (default: problem.steps) steps."""
     integ = integrator_for(problem, phis)
     return integ.run(problem.u0, problem.t0, problem.steps if steps is None else steps, callback)
+
+
+# ---------------------------------------------------------------------------
+# Exponential Rosenbrock-Euler for Riccati-type matrix equations
+# ---------------------------------------------------------------------------
+
+def riccati_rhs(U, A1, A2, B, C):
+    """f(U) = A1 U + U A2^T + C + U B U (section 1, eq. Riccati, in the matrix form
+    whose vec is K u + g(u) with K = A2 (+) A1, eq. ODE2d)."""
+    return A1 @ U + U @ A2.T + C + U @ B @ U
+
+
+def riccati_jacobian_directions(U, A1, A2, B):
+    """Directions of the Jacobian of ``riccati_rhs`` at U.
+
+    The derivative of f at U in direction V is A1 V + V A2^T + V B U + U B V
+    = J1 V + V J2^T with J1 = A1 + U B and J2 = A2 + (B U)^T, so the Jacobian is the
+    Kronecker sum J2 (+) J1 that the Rosenbrock-Euler phisplit scheme assumes
+    (section 3.2 before eq. expRosEulertensor; the Kronecker structure of the
+    Riccati Jacobian in section 4.1)."""
+    return A1 + U @ B, A2 + (B @ U).T
+
+
+def rosenbrock_euler_riccati_step(U, tau, A1, A2, B, C):
+    """One exponential Rosenbrock-Euler phisplit step (eq. expRosEulertensor):
+    U + (tau f(U)) x_1 phi_1(tau J1) x_2 phi_1(tau J2), with tau on the whole bracket
+    as in eq. expRosEuler.  A 2-tensor times M1 in mode 1 and M2 in mode 2 is
+    M1 V M2^T."""
+    from .phi import phi_functions
+    J1, J2 = riccati_jacobian_directions(U, A1, A2, B)
+    P1 = phi_functions(tau * J1, 1)[1]
+    P2 = phi_functions(tau * J2, 1)[1]
+    return U + P1 @ (tau * riccati_rhs(U, A1, A2, B, C)) @ P2.T
+
+
+def rosenbrock_euler_riccati_step_unsplit(U, tau, A1, A2, B, C):
+    """The same step with the exact phi_1 of the whole Jacobian K_n = I (x) J1 + J2 (x) I
+    (eq. expRosEuler on vec U, first index fastest): a dense brute force for tiny sizes."""
+    from .phi import phi_functions
+    n1, n2 = U.shape
+    J1, J2 = riccati_jacobian_directions(U, A1, A2, B)
+    Kn = np.kron(np.eye(n2), J1) + np.kron(J2, np.eye(n1))
+    f = riccati_rhs(U, A1, A2, B, C).reshape(-1, order="F")
+    u = U.reshape(-1, order="F") + tau * (phi_functions(tau * Kn, 1)[1] @ f)
+    return u.reshape((n1, n2), order="F")
+
+
+def run_rosenbrock_euler_riccati(U0, tau, steps, A1, A2, B, C):
+    U = np.array(U0, dtype=float)
+    for _ in range(steps):
+        U = rosenbrock_euler_riccati_step(U, tau, A1, A2, B, C)
+    return U
