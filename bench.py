@@ -130,8 +130,40 @@ def riccati_flops_per_step(insts) -> float:
     return tot
 
 
-def bench_riccati(args):
-    """64 Riccati-type instances, n1, n2 ~ U{32..512}, ETD2RK phisplit, FP64."""
+def rosenbrock_flops_per_step(insts, tau) -> float:
+    """Algorithmic flops of one Rosenbrock-Euler step of the batch: the Jacobian
+    directions and W (4 GEMMs), phi_1 of both directions (13 Taylor products and 2
+    per squaring, with the squarings that ||tau A_mu||_1 calls for, rounded up to
+    even as the device does), and the Tucker operator (2 GEMMs)."""
+    import numpy as np
+    total = 0.0
+    for x in insts:
+        n1, n2 = x.n1, x.n2
+        total += 2.0 * n1 * n2 * (n1 + n2) * 2 + 2.0 * n1 * n2 * (n1 + n2)
+        for A, n in ((x.A1, n1), (x.A2, n2)):
+            nu = tau * np.abs(A).sum(axis=0).max()
+            s = 0
+            while nu > 0.5:
+                nu *= 0.5
+                s += 1
+            s += s & 1
+            total += 2.0 * n**3 * (13 + 2 * s)
+    return total
+
+
+def batch_smax(insts, tau) -> int:
+    """Squaring phases per Rosenbrock-Euler step, as the plan fixes them."""
+    import numpy as np
+    nu = max(tau * np.abs(A).sum(axis=0).max() for x in insts for A in (x.A1, x.A2))
+    s = 0
+    while nu > 0.5 and s < 60:
+        nu *= 0.5
+        s += 1
+    return s + 4 + ((s + 4) & 1)
+
+
+def bench_riccati(args, scheme="etd2rk"):
+    """64 Riccati-type instances, n1, n2 ~ U{32..512}, ETD2RK or Rosenbrock-Euler phisplit, FP64."""
     import numpy as np
     import torch
     import paper_2304_02327_amd as px
@@ -141,7 +173,7 @@ def bench_riccati(args):
     insts = W.riccati_batch()
     tau = 1e-3
     t = time.perf_counter()
-    batch = px.RiccatiBatch(insts, tau, device=dev)
+    batch = px.RiccatiBatch(insts, tau, device=dev, scheme=scheme)
     setup_s = time.perf_counter() - t
     U0 = batch.state_to_device([x.U0 for x in insts])
     U = U0.clone()
@@ -163,19 +195,22 @@ def bench_riccati(args):
     stream.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    flops = riccati_flops_per_step(insts)
+    ros = scheme == "rosenbrock_euler"
+    flops = rosenbrock_flops_per_step(insts, tau) if ros else riccati_flops_per_step(insts)
     tf = flops * args.steps / (gpu_ms / 1e3) / 1e12
+    name = "Rosenbrock-Euler" if ros else "ETD2RK"
+    launches = (19 + batch_smax(insts, tau)) if ros else 10
     result = {
         "metric": METRIC, "value": N * args.steps / (gpu_ms / 1e3), "unit": "DOF-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": gpu_ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "64 Riccati-type instances, n1,n2 ~ U{32..512}, ETD2RK phisplit, FP64, tau=1e-3",
-                   "dof": N, "graph": True, "launches_per_step": 10},
+        "config": {"workload": f"64 Riccati-type instances, n1,n2 ~ U{{32..512}}, {name} phisplit, FP64, tau=1e-3",
+                   "dof": N, "graph": True, "launches_per_step": launches},
         "wall_s_timed_region": wall, "phi_setup_s": setup_s,
-        "roofline": {"kernel": "k_grouped_gemm (10 persistent FP64 MFMA launches per step)", "bound": "mfma",
-                     "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+        "roofline": {"kernel": f"k_grouped_gemm ({launches} persistent FP64 MFMA launches per step)",
+                     "bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                     "flops_per_step": flops, "avg_launch_us": round(gpu_ms * 1e3 / args.steps / 10, 3)},
+                     "flops_per_step": flops, "avg_launch_us": round(gpu_ms * 1e3 / args.steps / launches, 3)},
     }
     if not args.no_cpu_baseline:
         from oracle import nonlinear, schemes
@@ -187,10 +222,15 @@ def bench_riccati(args):
         for i in sample:
             x = insts[i]
             g = nonlinear.make_g("riccati", {"B": x.B, "C": x.C})
-            integs.append(schemes.Integrator([x.A1, x.A2], tau, "etd2rk", g))
+            if not ros:
+                integs.append(schemes.Integrator([x.A1, x.A2], tau, "etd2rk", g))
         osetup = time.perf_counter() - t
         t = time.perf_counter()
-        outs = [integ.run(insts[i].U0, 0.0, k) for integ, i in zip(integs, sample)]
+        if ros:
+            outs = [schemes.run_rosenbrock_euler_riccati(insts[i].U0, tau, k, insts[i].A1, insts[i].A2, insts[i].B,
+                                                          insts[i].C) for i in sample]
+        else:
+            outs = [integ.run(insts[i].U0, 0.0, k) for integ, i in zip(integs, sample)]
         secs = time.perf_counter() - t
         Ug = U0.clone()
         batch.run(Ug, k)
@@ -228,8 +268,10 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(sharding is described in the design notes only).", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "riccati64":
-        bench_riccati(args)
+    if args.workload in ("riccati64", "riccati64_ros"):
+        if args.steps is None:
+            args.steps = 20
+        bench_riccati(args, "rosenbrock_euler" if args.workload == "riccati64_ros" else "etd2rk")
         return
 
     import numpy as np

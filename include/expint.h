@@ -63,6 +63,8 @@ extern "C" {
 #define EXPINT_LAWSON2B      1  /* eq. lawson2tensor */
 #define EXPINT_EXP_EULER     2  /* eq. expEulertensor, split phi_1 */
 #define EXPINT_ETD2RK        3  /* eq. ETD2RKtensor with the (l!)^{d-1} split factor of eq. dsphi */
+#define EXPINT_ROSENBROCK_EULER 4  /* eq. expRosEulertensor; batched Riccati plans only (phi_1 of the
+                                      Jacobian directions rebuilt on the device at every step) */
 
 /* nonlinearities g(u) (autonomous) */
 #define EXPINT_G_NONE        0  /* g = 0 */
@@ -240,6 +242,25 @@ typedef struct expint_batch_plan expint_batch_plan;
 int expint_riccati_plan_create(expint_batch_plan** plan, int count, const int* n1, const int* n2,
                                const double* const* A1, const double* const* A2,
                                const double* B, const double* C, double tau);
+
+/*
+ * expint_riccati_plan_create_ex -- the same with a scheme: EXPINT_ETD2RK as
+ * above, or EXPINT_ROSENBROCK_EULER (eq. expRosEulertensor, tau on the whole
+ * bracket as in eq. expRosEuler).  The Jacobian of the right-hand side at U_n
+ * is the Kronecker sum of J1 = A1 + U_n B and J2 = A2 + (B U_n)^T (the
+ * structure section 4.1 states), and a step is
+ *     U <- U + phi_1(tau J1) W phi_1(tau J2)^T,   W = tau (A1 U + U A2^T + C + U B U).
+ * phi_1(tau J1) and phi_1(tau J2^T) = phi_1(tau J2)^T are built on the device
+ * at every step in FP64: scaling by the even power of two that brings the
+ * 1-norm to <= 1/2, the Taylor series of degree 13 by Horner (eq. seriesdef),
+ * and the squaring recurrence eq. squarephi.  The number of squaring phases
+ * per step is fixed at creation: the count ||tau A_mu||_1 needs plus 4; a
+ * Jacobian direction needing more is squared only that many times and loses
+ * accuracy.  Errors as expint_riccati_plan_create, and ENOTSUP for another scheme.
+ */
+int expint_riccati_plan_create_ex(expint_batch_plan** plan, int count, const int* n1, const int* n2,
+                                  const double* const* A1, const double* const* A2, const double* B,
+                                  const double* C, double tau, int scheme);
 
 /* expint_batch_state_size -- elements of the packed state (sum n1 n2). */
 int expint_batch_state_size(const expint_batch_plan* plan, size_t* elements);

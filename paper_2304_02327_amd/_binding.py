@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libexpint.so")
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5
 F64, C128 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_SLICED = 0, 1, 2, 3
+ROSENBROCK_EULER = 4  # batched Riccati plans only
 SCHEMES = {"lawson_euler": 0, "lawson2b": 1, "exp_euler": 2, "etd2rk": 3}
 NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3, "adr_paper": 4}
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "slice": PREC_SLICED}
@@ -62,6 +63,9 @@ def _load():
     lib.expint_riccati_plan_create.argtypes = [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_int),
                                                ctypes.POINTER(c_int), ctypes.POINTER(dp), ctypes.POINTER(dp),
                                                c_void_p, c_void_p, c_double]
+    lib.expint_riccati_plan_create_ex.argtypes = [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_int),
+                                                  ctypes.POINTER(c_int), ctypes.POINTER(dp), ctypes.POINTER(dp),
+                                                  c_void_p, c_void_p, c_double, c_int]
     lib.expint_batch_state_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
     lib.expint_batch_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
     lib.expint_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
@@ -80,7 +84,8 @@ EXPORTED_SYMBOLS = (
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_destroy", "expint_last_error",
     "expint_version",
-    "expint_riccati_plan_create", "expint_batch_state_size", "expint_batch_workspace_size",
+    "expint_riccati_plan_create", "expint_riccati_plan_create_ex", "expint_batch_state_size",
+    "expint_batch_workspace_size",
     "expint_batch_step", "expint_batch_run", "expint_batch_plan_destroy",
 )
 
@@ -332,15 +337,19 @@ def _unpack_colmajor(flat, shapes):
 
 
 class RiccatiBatch:
-    """ETD2RK phisplit for many instances of U' = A1 U + U A2^T + C + U B U.
+    """ETD2RK (default) or Rosenbrock-Euler phisplit for many instances of
+    U' = A1 U + U A2^T + C + U B U.
 
     ``instances`` hold natural-index host matrices (A1, A2, B, C, U0).  B and C
     are uploaded once and owned by this object; the state is one packed device
     array (instance i column-major at offset sum_{j<i} n1_j n2_j).
     """
 
-    def __init__(self, instances, tau: float, device="cuda"):
+    def __init__(self, instances, tau: float, device="cuda", scheme: str = "etd2rk"):
         import torch
+        if scheme not in ("etd2rk", "rosenbrock_euler"):
+            raise ValueError("batched Riccati schemes: 'etd2rk' or 'rosenbrock_euler'")
+        self.scheme = scheme
         self.n1 = [int(x.n1) for x in instances]
         self.n2 = [int(x.n2) for x in instances]
         self.count = len(instances)
@@ -355,8 +364,9 @@ class RiccatiBatch:
         n2 = (ctypes.c_int * self.count)(*self.n2)
         self._handle = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
-            _check(lib.expint_riccati_plan_create(ctypes.byref(self._handle), self.count, n1, n2, a1, a2,
-                                                  self.B.data_ptr(), self.C.data_ptr(), float(tau)))
+            _check(lib.expint_riccati_plan_create_ex(ctypes.byref(self._handle), self.count, n1, n2, a1, a2,
+                                                     self.B.data_ptr(), self.C.data_ptr(), float(tau),
+                                                     SCHEMES[scheme] if scheme == "etd2rk" else ROSENBROCK_EULER))
         size = ctypes.c_size_t(0)
         _check(lib.expint_batch_workspace_size(self._handle, ctypes.byref(size)))
         self.ws = torch.empty(max(size.value, 16), dtype=torch.uint8, device=self.device)

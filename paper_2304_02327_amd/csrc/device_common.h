@@ -20,6 +20,13 @@ __device__ __forceinline__ double zero<double>() { return 0.0; }
 template <>
 __device__ __forceinline__ cdouble zero<cdouble>() { return cdouble{0.0, 0.0}; }
 
+template <typename T>
+__device__ __forceinline__ T real_value(double c);
+template <>
+__device__ __forceinline__ double real_value<double>(double c) { return c; }
+template <>
+__device__ __forceinline__ cdouble real_value<cdouble>(double c) { return cdouble{c, 0.0}; }
+
 __device__ __forceinline__ double add(double a, double b) { return a + b; }
 __device__ __forceinline__ cdouble add(cdouble a, cdouble b) { return cdouble{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ double sub(double a, double b) { return a - b; }

@@ -40,6 +40,8 @@ enum EpiOp : int {
   EPI_ETD2RK_2 = 3,     // out0[e] = in1[e] + c * Y
   EPI_LAWSON2B_2 = 4,   // out0[e] = Y + c * g(in1[e])           (c = tau / 2)
   EPI_LINEAR = 5,       // out0[e] = alpha Y + beta in1[e] + c in2[e]   (in1 / in2 optional)
+  EPI_DIAG = 6,         // out0[e] = alpha Y + c [e mod ldiag == 0]: c added on the diagonal of a
+                        // square matrix output with leading dimension ldiag - 1
 };
 
 struct Epilogue {
@@ -50,6 +52,7 @@ struct Epilogue {
   const void* in1 = nullptr;   // secondary input
   const void* in2 = nullptr;   // third input (EPI_LINEAR)
   void* out1 = nullptr;        // secondary output
+  long ldiag = 1;              // EPI_DIAG: n + 1 for an n x n column-major output
   GridTime gt;                 // for EXPINT_G_ADR_PAPER
 };
 
@@ -65,8 +68,9 @@ int launch_mode_product(int dtype, long s, int n, long r, const void* M, const v
 // bk == 1 (B contiguous along k) or bq == 1 (contiguous along q) selects the
 // kernel.  `start` (device, count + 1 entries) holds the tile prefix sums.
 size_t gemm_desc_size();
+// gate (device int, optional): the descriptor's tiles run only while *gate > gate_level
 int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
-                   long ldc, const Epilogue& epi);
+                   long ldc, const Epilogue& epi, const int* gate = nullptr, int gate_level = 0);
 long gemm_desc_tiles(const void* desc);
 int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
                         void* stream);

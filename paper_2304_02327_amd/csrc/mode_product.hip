@@ -43,6 +43,8 @@ struct GemmArgs {
   long ldc;     // output element (m, q, batch) = batch * sC + m + ldc q
   long batches, tiles_m, tiles_q;
   Epilogue epi;
+  const int* gate = nullptr;  // grouped launches: tiles run only while *gate > gate_level
+  int gate_level = 0;
 };
 
 // Buffer loads: a resource covers exactly one operand (matrix, slab or whole
@@ -298,6 +300,7 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_grouped_gemm(const GemmArgs*
       else hi = mid - 1;
     }
     const GemmArgs g = descs[lo];
+    if (g.gate && *g.gate <= g.gate_level) continue;  // uniform over the workgroup
     __syncthreads();  // the previous tile's last LDS reads are done before this tile's stores
     gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ>(g, t - start[lo]);
   }
@@ -396,7 +399,7 @@ int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start
 size_t gemm_desc_size() { return sizeof(GemmArgs); }
 
 int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
-                   long ldc, const Epilogue& epi) {
+                   long ldc, const Epilogue& epi, const int* gate, int gate_level) {
   int tm, tq;
   grouped_tile_shape(&tm, &tq);
   GemmArgs g;
@@ -415,6 +418,8 @@ int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, l
   g.tiles_m = (M + tm - 1) / tm;
   g.tiles_q = (Q + tq - 1) / tq;
   g.epi = epi;
+  g.gate = gate;
+  g.gate_level = gate_level;
   std::memcpy(out, &g, sizeof(g));
   return EXPINT_OK;
 }

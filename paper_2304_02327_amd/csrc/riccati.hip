@@ -19,6 +19,28 @@
 //   10  U  = U2 + 2 P phi2(tau A2)^T
 // The association of U B U is chosen per instance so the middle product is
 // min(n1, n2) square.
+//
+// Exponential Rosenbrock-Euler (eq. expRosEulertensor, tau on the whole
+// bracket as in eq. expRosEuler) needs phi_1 of the Jacobian directions at
+// every step.  The Jacobian of f(U) = A1 U + U A2^T + C + U B U is the
+// Kronecker sum with directions J1 = A1 + U B and J2 = A2 + (B U)^T (the
+// structure section 4.1 states), and phi_1(tau J2)^T = phi_1(tau J2^T), so
+// with X1 = tau J1 and X2 = tau J2^T = tau (A2^T + B U) one step is
+//    U <- U + phi_1(X1) W phi_1(X2),   W = tau f(U) = tau A1 U + tau C + U X2
+// (U X2 = tau U A2^T + tau U B U).  The phases:
+//    R1  X1 = tau (A1 + U B),  X2 = tau (A2^T + B U)
+//    R2  W  = tau A1 U + tau C
+//    R3  W  = W + U X2
+//        k_phi_prep: s = the even power of two with ||X / 2^s||_1 <= 1/2,
+//        Y = X / 2^s, H = Y / 14! + I / 13!
+//    R4  twelve Horner steps H <- Y H + I / (k + 1)!  (k = 11 .. 0):
+//        H = phi_1(Y) by its Taylor series to degree 13 (eq. seriesdef;
+//        remainder below 2^-53 for ||Y||_1 <= 1/2)
+//    R5  E = I + Y H = e^Y
+//    R6  squarings (eq. squarephi): phi_1(2Y) = (phi_1(Y) e^Y + phi_1(Y)) / 2,
+//        e^{2Y} = e^Y e^Y; a matrix takes part in squaring p while s > p
+//    R7  P = phi_1(X1) W
+//    R8  U = U + P phi_1(X2)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +57,61 @@ using namespace expint;
 
 namespace {
 
-constexpr int kPhases = 10;
+constexpr int kPhases = 10;  // ETD2RK
+constexpr int kHorner = 12;  // Rosenbrock-Euler: Horner GEMM steps after the prep kernel
+
+// One matrix of the per-step phi_1 of the Rosenbrock-Euler scheme.
+struct PhiJob {
+  double* Y;  // in: X (n x n); out: X / 2^s
+  double* H;  // out: Y / 14! + I / 13!
+  int* s;     // out: the number of squarings (even, at most smax)
+  int n;
+};
+
+// One workgroup per matrix: the 1-norm (largest absolute column sum), the
+// scaling, and the first Horner term.
+__global__ __launch_bounds__(256) void k_phi_prep(const PhiJob* __restrict__ jobs, int smax) {
+  const PhiJob jb = jobs[blockIdx.x];
+  const int n = jb.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double colmax[4];
+  __shared__ int s_sh;
+  double mx = 0.0;
+  for (int c = wave; c < n; c += 4) {
+    double sum = 0.0;
+    for (int i = lane; i < n; i += 64) sum += fabs(jb.Y[i + (long)n * c]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    mx = (sum > mx || sum != sum) ? sum : mx;
+  }
+  if (lane == 0) colmax[wave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nu = colmax[0];
+    for (int w = 1; w < 4; ++w) nu = (colmax[w] > nu || colmax[w] != colmax[w]) ? colmax[w] : nu;
+    int sc = 0;
+    if (!(nu <= 1.7976931348623157e308)) {
+      sc = smax;  // inf or nan: the result is not finite either way
+    } else {
+      while (nu > 0.5 && sc < smax) {
+        nu *= 0.5;
+        ++sc;
+      }
+    }
+    sc += sc & 1;  // even: the squarings end in the buffer they start from
+    if (sc > smax) sc = smax;
+    s_sh = sc;
+    *jb.s = sc;
+  }
+  __syncthreads();
+  const double f = ldexp(1.0, -s_sh);
+  const double c14 = 1.0 / 87178291200.0, c13 = 1.0 / 6227020800.0;  // 1/14!, 1/13!
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += 256) {
+    const double y = jb.Y[e] * f;
+    jb.Y[e] = y;
+    jb.H[e] = y * c14 + ((e % (n + 1)) == 0 ? c13 : 0.0);
+  }
+}
 // phases whose B operand is contiguous along k (the others read M^T, contiguous along q)
 constexpr bool kPhaseBK[kPhases] = {true, true, true, false, true, false, true, true, true, false};
 
@@ -59,10 +135,23 @@ struct expint_batch_plan {
   double* dA2 = nullptr;      // A2, phi1(tau A2), phi2(tau A2) (each m2total)
   double* dP1b = nullptr;
   double* dP2b = nullptr;
-  // descriptors for the current (U, ws)
-  void* ddesc = nullptr;      // kPhases * count descriptors
-  long* dstart = nullptr;     // kPhases * (count + 1) tile prefix sums
-  long phase_tiles[kPhases] = {};
+  double* dA2T = nullptr;     // Rosenbrock-Euler: A2^T (m2total)
+  int scheme = EXPINT_ETD2RK;
+  int smax = 0;               // Rosenbrock-Euler: squaring phases per step
+  std::vector<int> morder;    // Rosenbrock-Euler: the 2 count matrices by decreasing size
+  // descriptors for the current (U, ws): one grouped launch per phase
+  struct Phase {
+    bool bk;                  // B operand contiguous along k
+    long first, start_off;    // first descriptor, offset of its tile prefix sums
+    int ndesc;
+    long tiles;
+  };
+  std::vector<Phase> phases;
+  int prep_after = -1;        // the phi prep kernel runs after this phase
+  void* ddesc = nullptr;
+  long* dstart = nullptr;
+  PhiJob* djobs = nullptr;
+  size_t desc_cap = 0, start_cap = 0;
   const void* d_U = nullptr;
   const void* d_ws = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -72,8 +161,9 @@ struct expint_batch_plan {
 namespace {
 
 void free_batch(expint_batch_plan* p) {
-  for (double* q : {p->dA1, p->dP1a, p->dP2a, p->dA2, p->dP1b, p->dP2b})
+  for (double* q : {p->dA1, p->dP1a, p->dP2a, p->dA2, p->dP1b, p->dP2b, p->dA2T})
     if (q) (void)hipFree(q);
+  if (p->djobs) (void)hipFree(p->djobs);
   if (p->ddesc) (void)hipFree(p->ddesc);
   if (p->dstart) (void)hipFree(p->dstart);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -92,12 +182,38 @@ Epilogue linear(void* out, double alpha, const void* in1 = nullptr, double beta 
   return e;
 }
 
-// Build the ten phases' descriptors for state U and workspace ws and upload them.
-int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
-  const size_t dsz = gemm_desc_size();
+// Descriptor lists of the phases, built on the host.
+struct PhaseBuilder {
+  size_t dsz = gemm_desc_size();
+  std::vector<char> desc;
+  std::vector<long> start;
+  std::vector<expint_batch_plan::Phase> phases;
+  char* open(bool bk) {  // a new phase
+    expint_batch_plan::Phase ph;
+    ph.bk = bk;
+    ph.first = (long)(desc.size() / dsz);
+    ph.start_off = (long)start.size();
+    ph.ndesc = 0;
+    ph.tiles = 0;
+    phases.push_back(ph);
+    start.push_back(0);
+    return nullptr;
+  }
+  char* add() {  // room for one more descriptor of the open phase
+    desc.resize(desc.size() + dsz);
+    return desc.data() + desc.size() - dsz;
+  }
+  void added() {  // after make_gemm_desc filled the last descriptor
+    auto& ph = phases.back();
+    ph.tiles += gemm_desc_tiles(desc.data() + desc.size() - dsz);
+    ph.ndesc += 1;
+    start.push_back(ph.tiles);
+  }
+};
+
+// ETD2RK: the ten phases listed at the top of this file.
+void build_etd2rk(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb) {
   const int cnt = p->count;
-  std::vector<char> host((size_t)kPhases * cnt * dsz);
-  std::vector<long> start((size_t)kPhases * (cnt + 1));
   double* T = reinterpret_cast<double*>(ws);
   double* Gn = T + p->ttotal;
   double* W = Gn + p->total;
@@ -106,7 +222,7 @@ int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
   double* W2 = U2 + p->total;
   const double tau = p->tau;
   for (int ph = 0; ph < kPhases; ++ph) {
-    long acc = 0;
+    pb.open(kPhaseBK[ph]);
     for (int slot = 0; slot < cnt; ++slot) {
       const int i = p->order[slot];
       const long n1 = p->n1[i], n2 = p->n2[i];
@@ -120,7 +236,7 @@ int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
       double *Gi = Gn + uo, *Wi = W + uo, *Pi = P + uo, *W2i = W2 + uo;
       const double *A1 = p->dA1 + p->moff1[i], *P1a = p->dP1a + p->moff1[i], *P2a = p->dP2a + p->moff1[i];
       const double *A2 = p->dA2 + p->moff2[i], *P1b = p->dP1b + p->moff2[i], *P2b = p->dP2b + p->moff2[i];
-      char* d = host.data() + ((size_t)ph * cnt + slot) * dsz;
+      char* d = pb.add();
       const double* Us = (ph < 6) ? Ui : U2i;  // state the phase reads (phases 7, 8 use U2)
       switch (ph) {
         case 0:
@@ -161,18 +277,144 @@ int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
           make_gemm_desc(d, Pi, n1, P2b, n2, 1, n1, n2, n2, n1, linear(Ui, 2.0, U2i, 1.0));
           break;
       }
-      start[(size_t)ph * (cnt + 1) + slot] = acc;
-      acc += gemm_desc_tiles(d);
+      pb.added();
     }
-    start[(size_t)ph * (cnt + 1) + cnt] = acc;
-    p->phase_tiles[ph] = acc;
+  }
+}
+
+// Rosenbrock-Euler: the phases R1 .. R8 listed at the top of this file.
+void build_rosenbrock(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb, std::vector<PhiJob>& jobs) {
+  const int cnt = p->count;
+  const double tau = p->tau;
+  double* W = reinterpret_cast<double*>(ws);
+  double* P = W + p->total;
+  double* m1 = P + p->total;         // Y, Ha, Hb, Ea, Eb of direction 1 (each m1total)
+  double* m2 = m1 + 5 * p->m1total;  // the same for direction 2 (each m2total)
+  int* sc = reinterpret_cast<int*>(m2 + 5 * p->m2total);  // 2 count squaring counts
+  // matrix j < cnt: direction 1 of instance j; j >= cnt: direction 2 of instance j - cnt
+  auto mat = [&](int j, int which) -> double* {  // which: 0 Y, 1 Ha, 2 Hb, 3 Ea, 4 Eb
+    if (j < cnt) return m1 + which * p->m1total + p->moff1[j];
+    return m2 + which * p->m2total + p->moff2[j - cnt];
+  };
+  auto msize = [&](int j) -> long { return j < cnt ? p->n1[j] : p->n2[j - cnt]; };
+  // R1: X1 = tau (A1 + U B), X2 = tau (A2^T + B U)
+  pb.open(true);
+  for (int slot = 0; slot < cnt; ++slot) {
+    const int i = p->order[slot];
+    const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
+    make_gemm_desc(pb.add(), U + uo, n1, p->B + uo, 1, n2, n1, n1, n2, n1,
+                   linear(mat(i, 0), tau, p->dA1 + p->moff1[i], tau));
+    pb.added();
+    make_gemm_desc(pb.add(), p->B + uo, n2, U + uo, 1, n1, n2, n2, n1, n2,
+                   linear(mat(cnt + i, 0), tau, p->dA2T + p->moff2[i], tau));
+    pb.added();
+  }
+  // R2: W = tau A1 U + tau C
+  pb.open(true);
+  for (int slot = 0; slot < cnt; ++slot) {
+    const int i = p->order[slot];
+    const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
+    make_gemm_desc(pb.add(), p->dA1 + p->moff1[i], n1, U + uo, 1, n1, n1, n2, n1, n1,
+                   linear(W + uo, tau, p->C + uo, tau));
+    pb.added();
+  }
+  // R3: W = W + U X2
+  pb.open(true);
+  for (int slot = 0; slot < cnt; ++slot) {
+    const int i = p->order[slot];
+    const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
+    make_gemm_desc(pb.add(), U + uo, n1, mat(cnt + i, 0), 1, n2, n1, n2, n2, n1, linear(W + uo, 1.0, W + uo, 1.0));
+    pb.added();
+  }
+  // the prep kernel follows R3
+  jobs.clear();
+  for (int j : p->morder) jobs.push_back(PhiJob{mat(j, 0), mat(j, 1), sc + j, (int)msize(j)});
+  auto diag = [](double* out, double c, long n) {
+    Epilogue e;
+    e.op = EPI_DIAG;
+    e.out0 = out;
+    e.alpha = 1.0;
+    e.c = c;
+    e.ldiag = n + 1;
+    return e;
+  };
+  // R4: Horner steps H <- Y H + I / (k + 1)!, k = 11 .. 0 (Ha -> Hb -> Ha ...)
+  double fact = 1.0;
+  std::vector<double> inv_fact(14);
+  for (int k = 0; k < 14; ++k) {
+    fact *= (k + 1);
+    inv_fact[k] = 1.0 / fact;  // 1 / (k + 1)!
+  }
+  for (int step = 0; step < kHorner; ++step) {
+    const int k = kHorner - 1 - step;
+    const int src = (step % 2 == 0) ? 1 : 2, dst = 3 - src;
+    pb.open(true);
+    for (int j : p->morder) {
+      const long n = msize(j);
+      make_gemm_desc(pb.add(), mat(j, 0), n, mat(j, src), 1, n, n, n, n, n, diag(mat(j, dst), inv_fact[k], n));
+      pb.added();
+    }
+  }
+  // R5: Ea = I + Y Ha
+  pb.open(true);
+  for (int j : p->morder) {
+    const long n = msize(j);
+    make_gemm_desc(pb.add(), mat(j, 0), n, mat(j, 1), 1, n, n, n, n, n, diag(mat(j, 3), 1.0, n));
+    pb.added();
+  }
+  // R6: squarings, gated by each matrix's count
+  for (int q = 0; q < p->smax; ++q) {
+    const int hc = (q % 2 == 0) ? 1 : 2, hn = 3 - hc;
+    const int ec = (q % 2 == 0) ? 3 : 4, en = 7 - ec;
+    pb.open(true);
+    for (int j : p->morder) {
+      const long n = msize(j);
+      make_gemm_desc(pb.add(), mat(j, hc), n, mat(j, ec), 1, n, n, n, n, n, linear(mat(j, hn), 0.5, mat(j, hc), 0.5),
+                     sc + j, q);
+      pb.added();
+      make_gemm_desc(pb.add(), mat(j, ec), n, mat(j, ec), 1, n, n, n, n, n, linear(mat(j, en), 1.0), sc + j, q);
+      pb.added();
+    }
+  }
+  // R7: P = phi_1(X1) W;  R8: U = U + P phi_1(X2)
+  pb.open(true);
+  for (int slot = 0; slot < cnt; ++slot) {
+    const int i = p->order[slot];
+    const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
+    make_gemm_desc(pb.add(), mat(i, 1), n1, W + uo, 1, n1, n1, n2, n1, n1, linear(P + uo, 1.0));
+    pb.added();
+  }
+  pb.open(true);
+  for (int slot = 0; slot < cnt; ++slot) {
+    const int i = p->order[slot];
+    const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
+    make_gemm_desc(pb.add(), P + uo, n1, mat(cnt + i, 1), 1, n2, n1, n2, n2, n1, linear(U + uo, 1.0, U + uo, 1.0));
+    pb.added();
+  }
+}
+
+// Build every phase's descriptors for state U and workspace ws and upload them.
+int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
+  PhaseBuilder pb;
+  std::vector<PhiJob> jobs;
+  if (p->scheme == EXPINT_ROSENBROCK_EULER) {
+    build_rosenbrock(p, U, ws, pb, jobs);
+    p->prep_after = 2;
+  } else {
+    build_etd2rk(p, U, ws, pb);
+    p->prep_after = -1;
   }
   // descriptors of an earlier (U, ws) pair may still be read by enqueued work
   if (p->d_U && hipDeviceSynchronize() != hipSuccess)
     return set_error(EXPINT_EHIP, "device synchronisation before a descriptor rebuild failed");
-  if (hipMemcpy(p->ddesc, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->dstart, start.data(), start.size() * sizeof(long), hipMemcpyHostToDevice) != hipSuccess)
+  if (pb.desc.size() > p->desc_cap || pb.start.size() > p->start_cap)
+    return set_error(EXPINT_EINVAL, "batched descriptors exceed the plan's capacity");
+  if (hipMemcpy(p->ddesc, pb.desc.data(), pb.desc.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->dstart, pb.start.data(), pb.start.size() * sizeof(long), hipMemcpyHostToDevice) != hipSuccess ||
+      (!jobs.empty() &&
+       hipMemcpy(p->djobs, jobs.data(), jobs.size() * sizeof(PhiJob), hipMemcpyHostToDevice) != hipSuccess))
     return set_error(EXPINT_EHIP, "upload of batched GEMM descriptors failed");
+  p->phases = pb.phases;
   p->d_U = U;
   p->d_ws = ws;
   if (p->gexec) {
@@ -184,11 +426,16 @@ int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
 
 int enqueue_batch_step(expint_batch_plan* p, hipStream_t s) {
   const size_t dsz = gemm_desc_size();
-  for (int ph = 0; ph < kPhases; ++ph) {
-    const char* d = static_cast<const char*>(p->ddesc) + (size_t)ph * p->count * dsz;
-    const long* st = p->dstart + (size_t)ph * (p->count + 1);
-    const int rc = launch_grouped_gemm(kPhaseBK[ph], d, st, p->count, p->phase_tiles[ph], s);
+  for (size_t k = 0; k < p->phases.size(); ++k) {
+    const auto& ph = p->phases[k];
+    const char* d = static_cast<const char*>(p->ddesc) + (size_t)ph.first * dsz;
+    const int rc = launch_grouped_gemm(ph.bk, d, p->dstart + ph.start_off, ph.ndesc, ph.tiles, s);
     if (rc != EXPINT_OK) return rc;
+    if ((int)k == p->prep_after) {
+      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(256), 0, s, p->djobs, p->smax);
+      const hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return set_error(EXPINT_EHIP, "phi prep launch failed: %s", hipGetErrorString(err));
+    }
   }
   return EXPINT_OK;
 }
@@ -204,11 +451,14 @@ int prepare(expint_batch_plan* p, double* U, void* ws) {
 
 }  // namespace
 
-extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const int* n2,
-                                          const double* const* A1, const double* const* A2, const double* B,
-                                          const double* C, double tau) {
+extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count, const int* n1, const int* n2,
+                                             const double* const* A1, const double* const* A2, const double* B,
+                                             const double* C, double tau, int scheme) {
   if (!out) return set_error(EXPINT_EINVAL, "plan output pointer is NULL");
   *out = nullptr;
+  if (scheme != EXPINT_ETD2RK && scheme != EXPINT_ROSENBROCK_EULER)
+    return set_error(EXPINT_ENOTSUP, "batched Riccati plans support ETD2RK and Rosenbrock-Euler (scheme %d)", scheme);
+  const bool ros = scheme == EXPINT_ROSENBROCK_EULER;
   if (count < 1 || !n1 || !n2 || !A1 || !A2 || !B || !C)
     return set_error(EXPINT_EINVAL, "need count >= 1 and non-NULL size, matrix and B/C arrays");
   if (!std::isfinite(tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
@@ -224,6 +474,7 @@ extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, co
   if (!p) return set_error(EXPINT_ENOMEM, "plan allocation failed");
   p->count = count;
   p->tau = tau;
+  p->scheme = scheme;
   p->B = B;
   p->C = C;
   p->n1.assign(n1, n1 + count);
@@ -258,13 +509,14 @@ extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, co
     const bool first = (job % 2) == 0;
     const int n = first ? n1[i] : n2[i];
     const double* A = first ? A1[i] : A2[i];
+    double* dstA = (first ? hA1.data() + p->moff1[i] : hA2.data() + p->moff2[i]);
+    std::memcpy(dstA, A, sizeof(double) * n * n);
+    if (ros) return;  // phi of the Jacobian directions is built on the device at every step
     std::vector<double> buf((size_t)3 * n * n);
     phi_setup_single_threaded(true);  // the jobs already run in parallel
     rcs[job] = phi_setup_real(n, A, n, tau, 2, buf.data(), n);
-    double* dstA = (first ? hA1.data() + p->moff1[i] : hA2.data() + p->moff2[i]);
     double* dst1 = (first ? hP1a.data() + p->moff1[i] : hP1b.data() + p->moff2[i]);
     double* dst2 = (first ? hP2a.data() + p->moff1[i] : hP2b.data() + p->moff2[i]);
-    std::memcpy(dstA, A, sizeof(double) * n * n);
     std::memcpy(dst1, buf.data() + (size_t)n * n, sizeof(double) * n * n);
     std::memcpy(dst2, buf.data() + (size_t)2 * n * n, sizeof(double) * n * n);
   };
@@ -292,14 +544,57 @@ extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, co
       rc = set_error(EXPINT_EHIP, "upload failed");
   };
   upload(&p->dA1, hA1);
-  upload(&p->dP1a, hP1a);
-  upload(&p->dP2a, hP2a);
   upload(&p->dA2, hA2);
-  upload(&p->dP1b, hP1b);
-  upload(&p->dP2b, hP2b);
-  if (rc == EXPINT_OK && (hipMalloc(&p->ddesc, (size_t)kPhases * count * gemm_desc_size()) != hipSuccess ||
-                          hipMalloc(reinterpret_cast<void**>(&p->dstart),
-                                    (size_t)kPhases * (count + 1) * sizeof(long)) != hipSuccess))
+  size_t ndesc = 0, nphase = 0;
+  if (!ros) {
+    upload(&p->dP1a, hP1a);
+    upload(&p->dP2a, hP2a);
+    upload(&p->dP1b, hP1b);
+    upload(&p->dP2b, hP2b);
+    ndesc = (size_t)kPhases * count;
+    nphase = kPhases;
+  } else {
+    // A2^T, the matrices by decreasing size, and the number of squaring phases:
+    // the largest count ||tau A_mu||_1 needs, plus 4 for the U B terms of the
+    // Jacobian (a matrix needing more is squared that many times only)
+    std::vector<double> hA2T(p->m2total);
+    double numax = 0.0;
+    for (int i = 0; i < count; ++i) {
+      const long m = n2[i];
+      for (long r = 0; r < m; ++r)
+        for (long c = 0; c < m; ++c) hA2T[p->moff2[i] + r + m * c] = A2[i][c + m * r];
+      for (int dir = 0; dir < 2; ++dir) {
+        const long n = dir ? n2[i] : n1[i];
+        const double* A = dir ? A2[i] : A1[i];
+        for (long c = 0; c < n; ++c) {
+          double sum = 0.0;
+          for (long r = 0; r < n; ++r) sum += std::fabs(A[r + n * c]);
+          numax = std::max(numax, std::fabs(tau) * sum);
+        }
+      }
+    }
+    int sc = 0;
+    while (numax > 0.5 && sc < 60) {
+      numax *= 0.5;
+      ++sc;
+    }
+    p->smax = sc + 4 + ((sc + 4) & 1);
+    upload(&p->dA2T, hA2T);
+    p->morder.resize(2 * count);
+    std::iota(p->morder.begin(), p->morder.end(), 0);
+    std::stable_sort(p->morder.begin(), p->morder.end(), [&](int a, int b) {
+      const int na = a < count ? n1[a] : n2[a - count], nb = b < count ? n1[b] : n2[b - count];
+      return na > nb;
+    });
+    ndesc = (size_t)count * (32 + 4 * p->smax);
+    nphase = 18 + p->smax;
+    if (rc == EXPINT_OK && hipMalloc(reinterpret_cast<void**>(&p->djobs), 2 * count * sizeof(PhiJob)) != hipSuccess)
+      rc = set_error(EXPINT_ENOMEM, "device allocation for phi jobs failed");
+  }
+  p->desc_cap = ndesc * gemm_desc_size();
+  p->start_cap = ndesc + nphase;
+  if (rc == EXPINT_OK && (hipMalloc(&p->ddesc, p->desc_cap) != hipSuccess ||
+                          hipMalloc(reinterpret_cast<void**>(&p->dstart), p->start_cap * sizeof(long)) != hipSuccess))
     rc = set_error(EXPINT_ENOMEM, "device allocation for descriptors failed");
   if (rc != EXPINT_OK) {
     free_batch(p);
@@ -310,6 +605,12 @@ extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, co
   return EXPINT_OK;
 }
 
+extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const int* n2,
+                                          const double* const* A1, const double* const* A2, const double* B,
+                                          const double* C, double tau) {
+  return expint_riccati_plan_create_ex(out, count, n1, n2, A1, A2, B, C, tau, EXPINT_ETD2RK);
+}
+
 extern "C" int expint_batch_state_size(const expint_batch_plan* p, size_t* elements) {
   if (!p || !elements) return set_error(EXPINT_EINVAL, "NULL plan or output");
   *elements = (size_t)p->total;
@@ -318,7 +619,10 @@ extern "C" int expint_batch_state_size(const expint_batch_plan* p, size_t* eleme
 
 extern "C" int expint_batch_workspace_size(const expint_batch_plan* p, size_t* bytes) {
   if (!p || !bytes) return set_error(EXPINT_EINVAL, "NULL plan or output");
-  *bytes = (size_t)(p->ttotal + 5 * p->total) * sizeof(double);
+  if (p->scheme == EXPINT_ROSENBROCK_EULER)
+    *bytes = (size_t)(2 * p->total + 5 * (p->m1total + p->m2total)) * sizeof(double) + 2 * p->count * sizeof(int);
+  else
+    *bytes = (size_t)(p->ttotal + 5 * p->total) * sizeof(double);
   return EXPINT_OK;
 }
 

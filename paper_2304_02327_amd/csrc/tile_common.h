@@ -62,6 +62,16 @@ __device__ __forceinline__ void epilogue_tile(const Epilogue& ep, Visit&& visit)
         visit([&](long e, T y) { out0[e] = add(y, scale(g1(ld<T>(ep.in1, e), e), ep.c)); });
       });
       break;
+    case EPI_DIAG: {
+      // square matrix outputs of at most 4096^2 elements: 32-bit index arithmetic
+      const unsigned ld = (unsigned)ep.ldiag;
+      visit([&](long e, T y) {
+        T v = scale(y, ep.alpha);
+        if ((unsigned)e % ld == 0u) v = add(v, real_value<T>(ep.c));
+        out0[e] = v;
+      });
+      break;
+    }
     case EPI_LINEAR:
       visit([&](long e, T y) {
         T v = scale(y, ep.alpha);

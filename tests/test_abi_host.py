@@ -209,5 +209,10 @@ def test_riccati_plan_rejects_bad_arguments():
     assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, n2, n2, mats, mats, 16, 16, float("inf")) == B.EINVAL
     big = (ctypes.c_int * 2)(5000, 4)
     assert B.lib.expint_riccati_plan_create(ctypes.byref(h), 2, big, n2, mats, mats, 16, 16, 0.1) == B.ENOTSUP
+    # schemes: ETD2RK and Rosenbrock-Euler only, checked before any device work
+    for scheme in (0, 1, 2, 5, -1):
+        assert B.lib.expint_riccati_plan_create_ex(ctypes.byref(h), 2, n2, n2, mats, mats, 16, 16, 0.1,
+                                                   scheme) == B.ENOTSUP
+    assert B.lib.expint_riccati_plan_create_ex(ctypes.byref(h), 0, n2, n2, mats, mats, 16, 16, 0.1, 4) == B.EINVAL
     assert h.value is None
     assert B.lib.expint_batch_step(None, None, None, None) == B.EINVAL
