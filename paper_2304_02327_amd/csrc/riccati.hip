@@ -68,17 +68,20 @@ struct PhiJob {
   int n;
 };
 
-// One workgroup per matrix: the 1-norm (largest absolute column sum), the
-// scaling, and the first Horner term.
-__global__ __launch_bounds__(256) void k_phi_prep(const PhiJob* __restrict__ jobs, int smax) {
+// One workgroup of 16 waves per matrix: the 1-norm (largest absolute column
+// sum), the scaling, and the first Horner term.  Wave w takes columns w, w + 16,
+// ...; lanes run down a column (coalesced).
+constexpr int kPrepWaves = 16;
+__global__ __launch_bounds__(64 * kPrepWaves) void k_phi_prep(const PhiJob* __restrict__ jobs, int smax) {
   const PhiJob jb = jobs[blockIdx.x];
   const int n = jb.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double colmax[4];
+  __shared__ double colmax[kPrepWaves];
   __shared__ int s_sh;
   double mx = 0.0;
-  for (int c = wave; c < n; c += 4) {
+  for (int c = wave; c < n; c += kPrepWaves) {
+    const double* col = jb.Y + (long)n * c;
     double sum = 0.0;
-    for (int i = lane; i < n; i += 64) sum += fabs(jb.Y[i + (long)n * c]);
+    for (int i = lane; i < n; i += 64) sum += fabs(col[i]);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
     mx = (sum > mx || sum != sum) ? sum : mx;
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(256) void k_phi_prep(const PhiJob* __restrict__ job
   __syncthreads();
   if (threadIdx.x == 0) {
     double nu = colmax[0];
-    for (int w = 1; w < 4; ++w) nu = (colmax[w] > nu || colmax[w] != colmax[w]) ? colmax[w] : nu;
+    for (int w = 1; w < kPrepWaves; ++w) nu = (colmax[w] > nu || colmax[w] != colmax[w]) ? colmax[w] : nu;
     int sc = 0;
     if (!(nu <= 1.7976931348623157e308)) {
       sc = smax;  // inf or nan: the result is not finite either way
@@ -105,14 +108,18 @@ __global__ __launch_bounds__(256) void k_phi_prep(const PhiJob* __restrict__ job
   __syncthreads();
   const double f = ldexp(1.0, -s_sh);
   const double c14 = 1.0 / 87178291200.0, c13 = 1.0 / 6227020800.0;  // 1/14!, 1/13!
-  const long nn = (long)n * n;
-  for (long e = threadIdx.x; e < nn; e += 256) {
-    const double y = jb.Y[e] * f;
-    jb.Y[e] = y;
-    jb.H[e] = y * c14 + ((e % (n + 1)) == 0 ? c13 : 0.0);
+  for (int c = wave; c < n; c += kPrepWaves) {
+    double* ycol = jb.Y + (long)n * c;
+    double* hcol = jb.H + (long)n * c;
+    for (int i = lane; i < n; i += 64) {
+      const double y = ycol[i] * f;
+      ycol[i] = y;
+      hcol[i] = y * c14 + (i == c ? c13 : 0.0);
+    }
   }
 }
-// phases whose B operand is contiguous along k (the others read M^T, contiguous along q)
+
+// ETD2RK phases whose B operand is contiguous along k (the others read M^T, contiguous along q)
 constexpr bool kPhaseBK[kPhases] = {true, true, true, false, true, false, true, true, true, false};
 
 }  // namespace
@@ -432,7 +439,7 @@ int enqueue_batch_step(expint_batch_plan* p, hipStream_t s) {
     const int rc = launch_grouped_gemm(ph.bk, d, p->dstart + ph.start_off, ph.ndesc, ph.tiles, s);
     if (rc != EXPINT_OK) return rc;
     if ((int)k == p->prep_after) {
-      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(256), 0, s, p->djobs, p->smax);
+      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(64 * kPrepWaves), 0, s, p->djobs, p->smax);
       const hipError_t err = hipGetLastError();
       if (err != hipSuccess) return set_error(EXPINT_EHIP, "phi prep launch failed: %s", hipGetErrorString(err));
     }
