@@ -79,10 +79,24 @@ def plan_kwargs(p):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mode_product_adr128_hbm_traffic.md")
 
 
+TRAFFIC_SOURCES = ("paper_2304_02327_amd/csrc/mode_product.hip", "paper_2304_02327_amd/csrc/tile_common.h",
+                   "paper_2304_02327_amd/csrc/device_common.h", "paper_2304_02327_amd/csrc/internal.h",
+                   "include/expint.h")
+
+
+def kernel_sources_sha256() -> str:
+    """SHA-256 over the sources the mu-mode product kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        h.update(rel.encode())
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str):
     """HBM bytes per mu-mode-product launch from the committed PMC summary, or None when
-    the workload differs or the kernel source changed since the counters were taken."""
-    import hashlib
+    the workload differs or the kernel's sources changed since the counters were taken."""
     if workload != "adr128" or not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
@@ -90,10 +104,7 @@ def measured_traffic(workload: str):
         if " = " in line:
             k, v = line.strip().split(" = ", 1)
             fields[k] = v
-    src = os.path.join(ROOT, fields.get("kernel_source", "missing"))
-    if not os.path.exists(src):
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernel_source_sha256"):
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -533,4 +544,7 @@ def cpu_baseline(p, plan, U0, budget_s):
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--kernel-sources-sha256":
+        print(kernel_sources_sha256())
+    else:
+        main()

@@ -22,6 +22,18 @@ __device__ __forceinline__ long xcd_remap(long L, long nt) {
 template <typename T>
 __device__ __forceinline__ T ld(const void* p, long i) { return static_cast<const T*>(p)[i]; }
 
+// Non-temporal store of a plain product (alpha Y, the intermediate tensors of
+// a Tucker chain and tucker_apply's output).  Measured on MI355X at 128^3: a
+// plain launch takes 15.6 instead of 16.7 us and an ETD2RK step 121 instead of
+// 125 us; the same stores on the stage outputs (U, U_n2, W_2), which the next
+// stage reads back at once, made the step slower (128 us), so those stay
+// ordinary stores.
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(cdouble* p, cdouble v) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2d{v.re, v.im}, reinterpret_cast<v2d*>(p));
+}
+
 // Applies the epilogue to the outputs a thread owns: visit(f) calls f(e, y)
 // for each of them.  The op and the nonlinearity are uniform per launch, so
 // they are dispatched once, outside the element loop: every path is a short
@@ -34,7 +46,7 @@ __device__ __forceinline__ void epilogue_tile(const Epilogue& ep, Visit&& visit)
       if (ep.beta != 0.0)
         visit([&](long e, T y) { out0[e] = add(scale(y, ep.alpha), scale(out0[e], ep.beta)); });
       else
-        visit([&](long e, T y) { out0[e] = scale(y, ep.alpha); });
+        visit([&](long e, T y) { st_stream(&out0[e], scale(y, ep.alpha)); });
       break;
     case EPI_EXP_EULER:
       visit([&](long e, T y) { out0[e] = add(ld<T>(ep.in1, e), y); });
