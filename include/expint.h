@@ -148,7 +148,7 @@ int tucker_workspace_size(int d, const int* n, int dtype, int precision, size_t*
 typedef struct expint_plan expint_plan;
 
 typedef struct expint_problem {
-  int d;                 /* 1..3 */
+  int d;                 /* 1..4 */
   int n[4];              /* n[0..d-1] */
   const double* A[4];    /* host, column-major n[mu] x n[mu] (complex: interleaved), lda = n[mu] */
   double tau;            /* constant step size */

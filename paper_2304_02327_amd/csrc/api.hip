@@ -521,7 +521,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if (!out) return set_error(EXPINT_EINVAL, "plan output pointer is NULL");
   *out = nullptr;
   if (!prob) return set_error(EXPINT_EINVAL, "problem is NULL");
-  if (prob->d < 1 || prob->d > 3) return set_error(EXPINT_EINVAL, "d = %d: need 1 <= d <= 3", prob->d);
+  if (prob->d < 1 || prob->d > 4) return set_error(EXPINT_EINVAL, "d = %d: need 1 <= d <= 4", prob->d);
   long N;
   TRY(validate_shape(prob->d, prob->n, &N));
   if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
   const T u = U[e];
   T acc = zero<T>();
   unsigned rem = e, stride = 1;
-  int idx[3] = {0, 0, 0};
+  int idx[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int mu = 0; mu < D; ++mu) {
     const unsigned nm = (unsigned)a.n[mu];
@@ -164,6 +164,9 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
       break;
     case 3:
       EXPINT_STENCIL_LAUNCH(3);
+      break;
+    case 4:
+      EXPINT_STENCIL_LAUNCH(4);
       break;
     default:
       return set_error(EXPINT_ENOTSUP, "stencil: d = %d not supported", st.d);
