@@ -96,6 +96,99 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil(StencilArgs a) {
   static_cast<T*>(a.W)[e] = scale(add(acc, gu), a.tau);
 }
 
+// Real data with n_1 a multiple of V: a thread takes V consecutive elements of
+// one i_1 row.  Its row segment and the neighbouring segments along i_2, i_3,
+// ... come in as 16-byte vector loads (the tensors are 16-byte aligned and each
+// segment starts at an even element), the two i_1 neighbours outside the
+// segment as single loads, and W leaves as vector stores: about 2.5x fewer
+// memory instructions than one thread per element.  The terms are summed in
+// the same order as in k_stage_stencil.
+template <int D, bool TOEP, int V>
+__global__ __launch_bounds__(kThreads) void k_stage_stencil_v(StencilArgs a) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  static_assert(V % 2 == 0, "segments are whole 16-byte vectors");
+  const unsigned groups = (unsigned)(a.N / V);
+  const unsigned gi = xcd_block(blockIdx.x, gridDim.x) * (unsigned)kThreads + threadIdx.x;
+  if (gi >= groups) return;
+  const unsigned e0 = gi * V;
+  const double* U = static_cast<const double*>(a.U);
+  auto seg = [&](unsigned at, double (&out)[V]) {
+#pragma unroll
+    for (int h = 0; h < V / 2; ++h) {
+      const v2d t = *reinterpret_cast<const v2d*>(U + at + 2 * h);
+      out[2 * h] = t[0];
+      out[2 * h + 1] = t[1];
+    }
+  };
+  double u[V], acc[V];
+  seg(e0, u);
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0.0;
+  // direction 1: neighbours inside the segment, plus one on either side
+  const unsigned n1 = (unsigned)a.n[0];
+  const unsigned i1 = e0 % n1;
+  unsigned rem = e0 / n1;
+  int idx[4] = {(int)i1, 0, 0, 0};
+  {
+    const double* c = static_cast<const double*>(a.coef[0]);
+    const bool has_lo = i1 > 0 || a.periodic[0], has_up = i1 + V < n1 || a.periodic[0];
+    const double left = i1 > 0 ? U[e0 - 1] : (a.periodic[0] ? U[e0 + n1 - 1] : 0.0);
+    const double right = i1 + V < n1 ? U[e0 + V] : (a.periodic[0] ? U[e0 + V - n1] : 0.0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double clo = TOEP ? a.tc[0][0][0] : c[i1 + v];
+      const double cdi = TOEP ? a.tc[0][1][0] : c[n1 + i1 + v];
+      const double cup = TOEP ? a.tc[0][2][0] : c[2 * n1 + i1 + v];
+      acc[v] = fma(cdi, u[v], acc[v]);
+      if (v > 0) acc[v] = fma(clo, u[v - 1], acc[v]);
+      else if (has_lo) acc[v] = fma(clo, left, acc[v]);
+      if (v < V - 1) acc[v] = fma(cup, u[v + 1], acc[v]);
+      else if (has_up) acc[v] = fma(cup, right, acc[v]);
+    }
+  }
+  unsigned stride = n1;
+#pragma unroll
+  for (int mu = 1; mu < D; ++mu) {
+    const unsigned nm = (unsigned)a.n[mu];
+    unsigned i;
+    if (mu < D - 1) {
+      i = rem % nm;
+      rem /= nm;
+    } else {
+      i = rem;
+    }
+    idx[mu] = (int)i;
+    const double* c = static_cast<const double*>(a.coef[mu]);
+    const double clo = TOEP ? a.tc[mu][0][0] : c[i];
+    const double cdi = TOEP ? a.tc[mu][1][0] : c[nm + i];
+    const double cup = TOEP ? a.tc[mu][2][0] : c[2 * nm + i];
+    double lo[V], up[V];
+    const bool has_lo = i > 0 || a.periodic[mu], has_up = i + 1 < nm || a.periodic[mu];
+    if (has_lo) seg(i > 0 ? e0 - stride : e0 + (nm - 1) * stride, lo);
+    if (has_up) seg(i + 1 < nm ? e0 + stride : e0 - (nm - 1) * stride, up);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      acc[v] = fma(cdi, u[v], acc[v]);
+      if (has_lo) acc[v] = fma(clo, lo[v], acc[v]);
+      if (has_up) acc[v] = fma(cup, up[v], acc[v]);
+    }
+    stride *= nm;
+  }
+  double w[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double gu;
+    if (D == 3 && a.g == EXPINT_G_ADR_PAPER)
+      gu = adr_paper_g(a.gt, u[v], clock_time(a.gt, 0.0), idx[0] + v, idx[1], idx[2]);
+    else
+      gu = g_eval(a.g, u[v], a.gparam);
+    w[v] = (acc[v] + gu) * a.tau;
+  }
+  double* W = static_cast<double*>(a.W);
+#pragma unroll
+  for (int h = 0; h < V / 2; ++h) *reinterpret_cast<v2d*>(W + e0 + 2 * h) = v2d{w[2 * h], w[2 * h + 1]};
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scaled_g(long N, const void* Uv, void* Wv, double s,
                                                        int g, double gp, GridTime gt) {
@@ -154,6 +247,37 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
   } else {                                                                                           \
     if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, D, false>), grid, block, 0, s, a);          \
     else hipLaunchKernelGGL((k_stage_stencil<double, D, false>), grid, block, 0, s, a);             \
+  }
+  // real data with n_1 a multiple of 4 (or 2): the vectorised kernel
+  const int V = c ? 1 : (st.n[0] % 4 == 0 ? 4 : (st.n[0] % 2 == 0 ? 2 : 1));
+  if (V > 1) {
+    const dim3 vgrid(blocks_for(N / V));
+#define EXPINT_STENCIL_V(D)                                                                        \
+  if (st.toeplitz) {                                                                                \
+    if (V == 4) hipLaunchKernelGGL((k_stage_stencil_v<D, true, 4>), vgrid, block, 0, s, a);        \
+    else hipLaunchKernelGGL((k_stage_stencil_v<D, true, 2>), vgrid, block, 0, s, a);               \
+  } else {                                                                                          \
+    if (V == 4) hipLaunchKernelGGL((k_stage_stencil_v<D, false, 4>), vgrid, block, 0, s, a);       \
+    else hipLaunchKernelGGL((k_stage_stencil_v<D, false, 2>), vgrid, block, 0, s, a);              \
+  }
+    switch (st.d) {
+      case 1:
+        EXPINT_STENCIL_V(1);
+        break;
+      case 2:
+        EXPINT_STENCIL_V(2);
+        break;
+      case 3:
+        EXPINT_STENCIL_V(3);
+        break;
+      case 4:
+        EXPINT_STENCIL_V(4);
+        break;
+      default:
+        return set_error(EXPINT_ENOTSUP, "stencil: d = %d not supported", st.d);
+    }
+#undef EXPINT_STENCIL_V
+    return check_launch("stage_stencil_v");
   }
   switch (st.d) {
     case 1:
