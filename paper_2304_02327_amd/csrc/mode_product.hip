@@ -339,11 +339,18 @@ int tile_override() {
 // real tile from 128^3 to 384^3 (69% of the FP64 MFMA peak at 384^3); complex
 // data, with four MFMAs per output block, does best on 64x64 / 8 waves.
 // Narrow M (short contiguous dimension) takes 32-row tiles to waste less.
-int choose_tile(bool cplx, long M) {
+// Measured choice (MI355X sweep over the table above).  Real data: 128 x 64
+// on 8 waves, unless that leaves fewer than two tiles per CU (256 CUs); then
+// 64 x 64 on 4 waves, whose twice as many workgroups overlap each other's
+// prologue and store burst (128^3: 15.2 instead of 15.8 us per launch).
+int choose_tile(bool cplx, long M, long Q, long batches) {
   const int o = tile_override();
   if (o >= 0) return o;
   if (cplx) return M >= 64 ? 6 : 2;
-  if (M >= 128) return 7;
+  if (M >= 128) {
+    const long big = ((M + 127) / 128) * ((Q + 63) / 64) * batches;
+    return big < 512 ? 0 : 7;
+  }
   if (M >= 64) return 6;
   return 2;
 }
@@ -351,7 +358,7 @@ int choose_tile(bool cplx, long M) {
 template <typename T, bool BK>
 int launch_choice(GemmArgs& g, hipStream_t st) {
   constexpr int KCR = std::is_same<T, cdouble>::value ? 8 : 16;
-  switch (choose_tile(std::is_same<T, cdouble>::value, g.M)) {
+  switch (choose_tile(std::is_same<T, cdouble>::value, g.M, g.Q, g.batches)) {
     case 1: return launch_tile<T, BK, 64, 32, KCR, 2, 2>(g, st);
     case 2: return launch_tile<T, BK, 32, 64, KCR, 2, 2>(g, st);
     case 3: return launch_tile<T, BK, 128, 64, KCR, 2, 2>(g, st);
