@@ -324,7 +324,7 @@ int launch_tile(GemmArgs& g, hipStream_t s) {
 // EXPINT_TILE set to one of these names overrides the automatic choice.
 const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128", "32x32",
                                   "64x64w8", "128x64w8", "128x128w8", "128x128", "128x64w8k32", "128x128w8k32",
-                                  "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4"};
+                                  "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4", "64x64k32"};
 constexpr int kNumTiles = sizeof(kTileNames) / sizeof(kTileNames[0]);
 
 int tile_override() {
@@ -374,6 +374,7 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
     case 13: return launch_tile<T, BK, 128, 64, KCR, 4, 2, 4>(g, st);
     case 14: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 3>(g, st);
     case 15: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 4>(g, st);
+    case 16: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 2>(g, st);
     default: return launch_tile<T, BK, 64, 64, KCR, 2, 2>(g, st);
   }
 }

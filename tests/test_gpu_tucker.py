@@ -95,7 +95,7 @@ def test_rejects_aliasing_and_short_workspace():
 @pytest.mark.parametrize("tile", ["64x64", "64x32", "32x64", "128x64", "64x128", "32x32",
                                   "64x64w8", "128x64w8", "128x128w8", "128x128", "128x64w8k32",
                                   "128x128w8k32", "128x64w8p3", "128x64w8p4", "64x64w8p3",
-                                  "64x64w8p4"])
+                                  "64x64w8p4", "64x64k32"])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_every_tile_shape(tile, cplx, monkeypatch):
     """Each tile shape the launcher can pick (forced through EXPINT_TILE) on ragged sizes."""
