@@ -17,14 +17,20 @@ against the paper rather than for speed):
                    vecexp, tuckerexp, forloop).
 * ``nonlinear`` -- the nonlinearities g of the workloads.
 * ``schemes``   -- Lawson-Euler, Lawson2b, exponential Euler and ETD2RK in
-                   the tensor (phisplit) form of section 3.2.
+                   the tensor (phisplit) form of section 3.2, and exponential
+                   Rosenbrock-Euler for Riccati-type matrix equations (eq.
+                   expRosEulertensor with the Kronecker-sum Jacobian).
 * ``norms``     -- error measures and the observed order.
 
 Parity status: every function is pinned by the tests under
 ``tests/test_oracle_*.py`` (brute force on tiny sizes, closed forms, the
-paper's printed errors of section 4.2, invariants).  None is "parity unpinned"
-except the batched Riccati stepping, whose only pins are dense brute force on
-small instances and invariants (no printed values exist).
+paper's printed errors of section 4.2, invariants; for Rosenbrock-Euler the
+Jacobian against central differences, the unsplit step with the exact phi_1 of
+the assembled Jacobian, and the order against a Runge-Kutta reference).  The
+Riccati steppers have no printed values to reproduce (the paper's Riccati
+experiment needs a reference solution it does not specify); their pins are
+dense brute force on small instances, the matrix form against the vec form,
+and these invariants.
 """
 
 from . import phi, tensor, nonlinear, schemes, norms  # noqa: F401

@@ -64,6 +64,7 @@ void mode_view(int d, const int* n, int mu, long* s, long* r) {
 // With a reduced contraction precision the inner modes keep FP32
 // intermediates in the ping-pong buffers (half the bytes of FP64) and the
 // last mode returns to FP64 through its epilogue.
+
 // Exact-slice chain: per mode, the digits of the current tensor along that
 // mode go to dig_ws, and the int8 product writes the FP64 result to t0 (the
 // slice kernel has consumed t0 before the product overwrites it).

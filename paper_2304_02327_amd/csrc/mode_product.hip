@@ -10,10 +10,10 @@
 // Either way Aop and the output have m as the stride-1 index, so loads and
 // stores run along contiguous memory (the non-contiguous mode is the K loop).
 //
-// Tiling: a 256-thread workgroup (4 wave64) owns a TM x TQ output tile and
-// walks K in chunks of KC, double-buffered in LDS with register prefetch of
-// the next chunk.  Each wave owns a (TM/2) x (TQ/2) sub-tile made of 16x16
-// MFMA blocks.  v_mfma_f64_16x16x4 leaves D[i][j] in lane j + 16 (i mod 4),
+// Tiling: a workgroup of WGM x WGQ wave64s (4 or 8) owns a TM x TQ output
+// tile and walks K in chunks of KC, double-buffered in LDS with register
+// prefetch of the next chunks.  Each wave owns a (TM/WGM) x (TQ/WGQ) sub-tile
+// made of 16x16 MFMA blocks.  v_mfma_f64_16x16x4 leaves D[i][j] in lane j + 16 (i mod 4),
 // register i / 4; the B-chunk fragment is passed as the instruction's first
 // operand so that 16 consecutive output rows m land in 16 consecutive lanes
 // (128-byte store segments).  The last mode's epilogue fuses the stage
