@@ -45,7 +45,16 @@ struct GemmArgs {
   Epilogue epi;
   const int* gate = nullptr;  // grouped launches: tiles run only while *gate > gate_level
   int gate_level = 0;
+  int m_fastest = 0;  // tile order, set with the tile counts (tile_coord)
 };
+
+// Bop is shared by all batches, Aop only when sA == 0: the M tile runs fastest
+// when Bop holds more data than all of Aop.
+static void set_tile_counts(GemmArgs& g, long TM, long TQ) {
+  g.tiles_m = (g.M + TM - 1) / TM;
+  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  g.m_fastest = g.Q > g.M * (g.sA ? g.batches : 1);
+}
 
 // Buffer loads: a resource covers exactly one operand (matrix, slab or whole
 // tensor), so a read past its end returns zero in hardware.  A K index past
@@ -84,10 +93,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   __shared__ double As[2][NP][KC * LDA_S];
   __shared__ double Bs[2][NP][KC * LDB_S];
 
-  const long tq = T_ % g.tiles_q;
-  const long rest = T_ / g.tiles_q;
-  const long tm = rest % g.tiles_m;
-  const long b = rest / g.tiles_m;
+  const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
+  const long tm = tc.tm, tq = tc.tq, b = tc.b;
   const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
   const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
   const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
@@ -308,8 +315,7 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_grouped_gemm(const GemmArgs*
 
 template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2>
 int launch_tile(GemmArgs& g, hipStream_t s) {
-  g.tiles_m = (g.M + TM - 1) / TM;
-  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  set_tile_counts(g, TM, TQ);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
@@ -423,11 +429,10 @@ int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, l
   g.sC = 0;
   g.ldc = ldc;
   g.batches = 1;
-  g.tiles_m = (M + tm - 1) / tm;
-  g.tiles_q = (Q + tq - 1) / tq;
   g.epi = epi;
   g.gate = gate;
   g.gate_level = gate_level;
+  set_tile_counts(g, tm, tq);
   std::memcpy(out, &g, sizeof(g));
   return EXPINT_OK;
 }
@@ -581,8 +586,8 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_f32(GemmArgs g)
 
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   const long T_ = xcd_remap((long)blockIdx.x, nt);
-  const long tq = T_ % g.tiles_q, rest = T_ / g.tiles_q;
-  const long tm = rest % g.tiles_m, b = rest / g.tiles_m;
+  const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
+  const long tm = tc.tm, tq = tc.tq, b = tc.b;
   const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
   const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
   const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
@@ -745,8 +750,8 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs
 
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   const long T_ = xcd_remap((long)blockIdx.x, nt);
-  const long tq = T_ % g.tiles_q, rest = T_ / g.tiles_q;
-  const long tm = rest % g.tiles_m, b = rest / g.tiles_m;
+  const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
+  const long tm = tc.tm, tq = tc.tq, b = tc.b;
   const int m0 = (int)(tm * TM), q0 = (int)(tq * TQ);
   const int Mi = (int)g.M, Qi = (int)g.Q, Ki = (int)g.K;
   const unsigned lda = (unsigned)g.lda, bk = (unsigned)g.bk, bq = (unsigned)g.bq;
@@ -903,8 +908,7 @@ int launch_lp_typed(GemmArgs& g, hipStream_t s) {
   // FP32: 128x64 on 8 waves (as FP64); BF16X3: 64x64 on 4 waves (the hi/lo split
   // needs the registers of two prefetched chunks of 8-element groups)
   constexpr int TM = PREC == EXPINT_PREC_FP32 ? 128 : 64, TQ = 64;
-  g.tiles_m = (g.M + TM - 1) / TM;
-  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  set_tile_counts(g, TM, TQ);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
@@ -932,8 +936,7 @@ int launch_lp_prec(bool v32, GemmArgs& g, bool mode1, hipStream_t s) {
 template <typename TA, typename TB, bool OUT32, bool BK>
 int launch_c64_typed(GemmArgs& g, hipStream_t s) {
   constexpr int TM = 64, TQ = 64;
-  g.tiles_m = (g.M + TM - 1) / TM;
-  g.tiles_q = (g.Q + TQ - 1) / TQ;
+  set_tile_counts(g, TM, TQ);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);

@@ -275,6 +275,7 @@ struct SliceGemmArgs {
   long M, Q;
   long sC, ldc;  // output element (m, q, b) = b sC + m + ldc q
   long batches, tiles_m, tiles_q;
+  int m_fastest;  // tile order (tile_coord): Bop holds more data than all of Aop
   Epilogue epi;
 };
 
@@ -302,8 +303,8 @@ __global__ __launch_bounds__(64 * WGM * WGQ, 2) void k_sliced_gemm(SliceGemmArgs
 
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   const long T_ = xcd_remap((long)blockIdx.x, nt);
-  const long tq = T_ % g.tiles_q, rest = T_ / g.tiles_q;
-  const long tm = rest % g.tiles_m, b = rest / g.tiles_m;
+  const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
+  const long tm = tc.tm, tq = tc.tq, b = tc.b;
   const long m0 = tm * TM, q0 = tq * TQ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave % WGM) * 32, wq0 = (wave / WGM) * 32;
@@ -409,6 +410,7 @@ int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
   constexpr int TM = 64, TQ = 64;  // 2 x 2 waves of 32 x 32
   g.tiles_m = (g.M + TM - 1) / TM;
   g.tiles_q = (g.Q + TQ - 1) / TQ;
+  g.m_fastest = g.Q > g.M * (g.a_rpb ? g.batches : 1);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "sliced product: too many tiles (%ld)", nt);

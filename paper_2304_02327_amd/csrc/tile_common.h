@@ -19,6 +19,22 @@ __device__ __forceinline__ long xcd_remap(long L, long nt) {
   return (L % X) * per + L / X;
 }
 
+// Coordinates (M tile, Q tile, batch) of tile t.  Neighbouring indices, which
+// xcd_remap keeps on one XCD and dispatches together, share a panel of the
+// larger operand, so its second reader finds it in that XCD's L2: with
+// m_fastest (Bop larger than all of Aop, as the tensor in a mode-1 product)
+// the M tile runs fastest and neighbours share a Bop panel; otherwise the Q
+// tile runs fastest and they share an Aop panel.
+struct TileCoord {
+  long tm, tq, b;
+};
+__device__ __forceinline__ TileCoord tile_coord(long t, long tiles_m, long tiles_q, int m_fastest) {
+  const long mq = tiles_m * tiles_q;
+  const long r = t % mq;
+  if (m_fastest) return {r % tiles_m, r / tiles_m, t / mq};
+  return {r / tiles_q, r % tiles_q, t / mq};
+}
+
 template <typename T>
 __device__ __forceinline__ T ld(const void* p, long i) { return static_cast<const T*>(p)[i]; }
 
