@@ -76,10 +76,11 @@ def plan_kwargs(p):
     return {}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_mode_product_adr128_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_modes12_adr128_hbm_traffic.md")
 
 
-TRAFFIC_SOURCES = ("paper_2304_02327_amd/csrc/mode_product.hip", "paper_2304_02327_amd/csrc/tile_common.h",
+TRAFFIC_SOURCES = ("paper_2304_02327_amd/csrc/modes12.hip", "paper_2304_02327_amd/csrc/mode_product.hip",
+                   "paper_2304_02327_amd/csrc/tile_common.h",
                    "paper_2304_02327_amd/csrc/device_common.h", "paper_2304_02327_amd/csrc/internal.h",
                    "include/expint.h")
 
@@ -95,7 +96,7 @@ def kernel_sources_sha256() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per mu-mode-product launch from the committed PMC summary, or None when
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary, or None when
     the workload differs or the kernel's sources changed since the counters were taken."""
     if workload != "adr128" or not os.path.exists(TRAFFIC_FILE):
         return None
@@ -422,9 +423,10 @@ def main():
 
 
 def tucker_roofline(args, p, px, dev, stream, U0):
-    """Roofline of the dominant kernel, the mu-mode product: tucker_apply with the
-    shapes and launch configuration of the step (the phi_1 Tucker), timed alone with
-    HIP events on the stream it is launched on."""
+    """Roofline of the dominant kernel: the fused launch of modes 1 and 2 where the
+    Tucker operator uses it (FP64 real data, n_2 <= 128), else the mu-mode product.
+    tucker_apply with the shapes and launch configuration of the step (the phi_1
+    Tucker), timed alone with HIP events on the stream it is launched on."""
     import torch
     ell = 1 if p.scheme in ("exp_euler", "etd2rk") else 0
     Ms = [px.matrix_to_device(px.phi_setup(a, p.tau, ell)[ell], device=dev) for a in p.A]
@@ -434,22 +436,50 @@ def tucker_roofline(args, p, px, dev, stream, U0):
                  "slice": px.PREC_SLICED}[args.precision]
     ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64, prec_code), 16),
                      dtype=torch.uint8, device=dev)
-    with torch.cuda.stream(stream):
-        for _ in range(3):
-            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
-        k0 = torch.cuda.Event(enable_timing=True)
-        k1 = torch.cuda.Event(enable_timing=True)
-        k0.record(stream)
-        for _ in range(args.kernel_reps):
-            px.tucker_apply(Ms, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
-        k1.record(stream)
-    stream.synchronize()
-    launches = args.kernel_reps * p.d
-    avg_launch_s = k0.elapsed_time(k1) / 1e3 / launches
-    flops_per_launch = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n) / p.d
-    achieved_tf = flops_per_launch / avg_launch_s / 1e12
+    def time_per_call(mats):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                px.tucker_apply(mats, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
+            k0 = torch.cuda.Event(enable_timing=True)
+            k1 = torch.cuda.Event(enable_timing=True)
+            k0.record(stream)
+            for _ in range(args.kernel_reps):
+                px.tucker_apply(mats, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
+            k1.record(stream)
+        stream.synchronize()
+        return k0.elapsed_time(k1) / 1e3 / args.kernel_reps
+
+    dt_code = px.C128 if p.is_complex else px.F64
+    fused12 = args.precision == "fp64" and px.tucker_fuses_modes12(p.n, dt_code, prec_code)
     esz = 16 if p.is_complex else 8
-    if args.precision == "fp64":
+    if fused12:
+        # the dominant kernel is the fused launch of modes 1 and 2 (M_3.. = identity:
+        # one launch per call, storing plainly as inside the step)
+        avg_launch_s = time_per_call(list(Ms[:2]) + [None] * (p.d - 2))
+        flops_per_launch = 2 * p.N * (p.n[0] + p.n[1])
+    else:
+        avg_launch_s = time_per_call(Ms) / p.d
+        flops_per_launch = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n) / p.d
+    achieved_tf = flops_per_launch / avg_launch_s / 1e12
+    if fused12:
+        alg_bytes = 2 * esz * p.N + esz * (p.n[0] ** 2 + p.n[1] ** 2)
+        roofline = {
+            "kernel": "k_modes12 (modes 1 and 2 of the Tucker operator in one launch, FP64 MFMA)",
+            "bound": "mfma",
+            "achieved": round(achieved_tf, 3),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
+            "traffic": measured_traffic(args.workload),
+        }
+        if p.d > 2:  # the remaining single-mode launches, timed alone beside it
+            rest_s = time_per_call([None, None] + list(Ms[2:]))
+            rest_flops = sum(2 * p.N * nm for nm in p.n[2:])
+            roofline["other_kernels"] = {
+                "k_mode_product (modes 3..d, one launch each)": {
+                    "avg_launch_us": round(rest_s / (p.d - 2) * 1e6, 3),
+                    "achieved_tflops": round(rest_flops / rest_s / 1e12, 3)}}
+    elif args.precision == "fp64":
         alg_bytes = 2 * esz * p.N
         roofline = {
             "kernel": "k_mode_product (FP64 MFMA mu-mode product)",

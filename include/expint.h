@@ -141,6 +141,16 @@ int tucker_apply(int d, const int* n, const void* const* M, const void* V, void*
  * more).  Errors: EINVAL for a bad shape, dtype or precision. */
 int tucker_workspace_size(int d, const int* n, int dtype, int precision, size_t* bytes);
 
+/* tucker_fuses_modes12 -- *fused = 1 if a Tucker operator of this shape, with
+ * M_1 and M_2 both present, runs modes 1 and 2 as one launch: FP64 real data
+ * at EXPINT_PREC_FP64 with n[1] <= 128 and n[0] <= 4096, d >= 2.  The launch
+ * computes M_1 V_b M_2^T for every n[0] x n[1] slab V_b with the intermediate
+ * in on-chip memory (the same sums in the same order as two mode products).
+ * The environment variable EXPINT_FUSE12=0 turns it off; EXPINT_TILE, which
+ * forces a single-mode tile shape, does too.  Errors: EINVAL for a bad shape,
+ * dtype, precision or a NULL fused. */
+int tucker_fuses_modes12(int d, const int* n, int dtype, int precision, int* fused);
+
 /* ------------------------------------------------------------------------ */
 /* plans and time stepping                                                   */
 /* ------------------------------------------------------------------------ */

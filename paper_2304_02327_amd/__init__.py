@@ -25,5 +25,6 @@ from ._binding import (  # noqa: F401
     tensor_to_device,
     tucker_apply,
     tucker_workspace_size,
+    tucker_fuses_modes12,
     version,
 )

@@ -52,6 +52,7 @@ def _load():
     lib.tucker_apply.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
                                  c_double, c_double, c_int, c_int, c_void_p, c_size_t, c_void_p]
     lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_size_t)]
+    lib.tucker_fuses_modes12.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_int)]
     lib.expint_plan_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_void_p]
     lib.expint_plan_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
     lib.expint_plan_set_phi.argtypes = [c_void_p, c_int, c_int, dp]
@@ -80,7 +81,7 @@ def _load():
 lib = _load()
 
 EXPORTED_SYMBOLS = (
-    "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size",
+    "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size", "tucker_fuses_modes12",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_destroy", "expint_last_error",
     "expint_version",
@@ -200,6 +201,16 @@ def tucker_workspace_size(n: Sequence[int], dtype: int = F64, precision=PREC_FP6
     out = ctypes.c_size_t(0)
     _check(lib.tucker_workspace_size(d, arr, dtype, _precision_code(precision), ctypes.byref(out)))
     return out.value
+
+
+def tucker_fuses_modes12(n: Sequence[int], dtype: int = F64, precision=PREC_FP64) -> bool:
+    """True if a Tucker operator of these sizes (M_1 and M_2 present) runs modes 1
+    and 2 as one launch."""
+    d = len(n)
+    arr = (ctypes.c_int * d)(*n)
+    out = ctypes.c_int(0)
+    _check(lib.tucker_fuses_modes12(d, arr, dtype, _precision_code(precision), ctypes.byref(out)))
+    return bool(out.value)
 
 
 def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,

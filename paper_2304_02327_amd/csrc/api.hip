@@ -55,6 +55,14 @@ void mode_view(int d, const int* n, int mu, long* s, long* r) {
   *r = b;
 }
 
+// Modes 1 and 2 run as one launch (FP64 real data, n2 <= 128) unless
+// EXPINT_FUSE12=0, or EXPINT_TILE forces a single-mode tile on every mode.
+bool fuse12_allowed(int dtype, int precision, int d, const int* n) {
+  const char* fenv = std::getenv("EXPINT_FUSE12");
+  return precision == EXPINT_PREC_FP64 && dtype == EXPINT_F64 && d >= 2 && modes12_fits(n[0], n[1]) &&
+         !(fenv && fenv[0] == '0') && !std::getenv("EXPINT_TILE");
+}
+
 // Tucker chain V x_1 M_1 ... x_d M_d with ping-pong buffers; the last applied
 // mode writes through `last` (its out0 and the other fields); earlier modes
 // store plainly.  Modes whose matrix is NULL are skipped.  If every matrix is
@@ -106,9 +114,30 @@ int tucker_chain(int dtype, int precision, int d, const int* n, const void* cons
   bool src32 = false;
   void* bufs[2] = {t0, t1};
   int which = 0;
+  // When mode 2 is the last one the fused launch writes the chain's output,
+  // which must then not be the input.
+  const bool fuse12 = fuse12_allowed(dtype, precision, d, n) && M[0] && M[1] &&
+                      (lastmu != 1 || (last.out0 != V && last.out1 != V));
   for (int mu = 0; mu < d; ++mu) {
     if (!M[mu]) continue;
     long s, r;
+    if (mu == 0 && fuse12) {
+      mode_view(d, n, 1, &s, &r);
+      if (lastmu == 1) {
+        TRY(launch_modes12(n[0], n[1], r, M[0], M[1], src, last, stream));
+      } else {
+        Epilogue e;
+        e.op = EPI_AXPBY;
+        e.alpha = 1.0;
+        e.beta = 0.0;
+        e.out0 = bufs[which];
+        TRY(launch_modes12(n[0], n[1], r, M[0], M[1], src, e, stream));
+        src = bufs[which];
+        which ^= 1;
+      }
+      mu = 1;
+      continue;
+    }
     mode_view(d, n, mu, &s, &r);
     if (mu == lastmu) {
       if (lp)
@@ -220,6 +249,16 @@ extern "C" int tucker_workspace_size(int d, const int* n, int dtype, int precisi
   size_t t, g, m;
   TRY(tucker_ws_layout(d, n, N, dtype, precision, d, &t, &g, &m));
   *bytes = t + g + m;
+  return EXPINT_OK;
+}
+
+extern "C" int tucker_fuses_modes12(int d, const int* n, int dtype, int precision, int* fused) {
+  long N;
+  TRY(validate_shape(d, n, &N));
+  if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
+  if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", precision);
+  if (!fused) return set_error(EXPINT_EINVAL, "fused is NULL");
+  *fused = fuse12_allowed(dtype, precision, d, n) ? 1 : 0;
   return EXPINT_OK;
 }
 

@@ -62,6 +62,15 @@ struct Epilogue {
 int launch_mode_product(int dtype, long s, int n, long r, const void* M, const void* V,
                         const Epilogue& epi, void* stream);
 
+// Modes 1 and 2 of a Tucker operator in one launch (FP64, real data): for
+// each of the r slabs V_b of n1 x n2 (first index fastest), M1 V_b M2^T goes
+// through the epilogue at the slab's own positions.  M1 and M2 are n1 x n1 and
+// n2 x n2 column-major (device).  The output must not overlap V.
+constexpr int kModes12MaxN1 = 4096, kModes12MaxN2 = 128;
+bool modes12_fits(int n1, int n2);
+int launch_modes12(int n1, int n2, long r, const void* M1, const void* M2, const void* V, const Epilogue& epi,
+                   void* stream);
+
 // Grouped FP64 GEMMs in one persistent launch (batched instances).  A
 // descriptor describes C[m, q] = sum_k A[m + lda k] B[k bk + q bq] for
 // m < M, q < Q, k < K with output element m + ldc q and an epilogue;

@@ -216,3 +216,32 @@ def test_riccati_plan_rejects_bad_arguments():
     assert B.lib.expint_riccati_plan_create_ex(ctypes.byref(h), 0, n2, n2, mats, mats, 16, 16, 0.1, 4) == B.EINVAL
     assert h.value is None
     assert B.lib.expint_batch_step(None, None, None, None) == B.EINVAL
+
+
+def test_fused_modes12_query(monkeypatch):
+    """Which shapes run modes 1 and 2 as one launch (FP64 real data, n2 <= 128,
+    n1 <= 4096, d >= 2), and the switches that turn it off."""
+    monkeypatch.delenv("EXPINT_FUSE12", raising=False)
+    monkeypatch.delenv("EXPINT_TILE", raising=False)
+    assert px.tucker_fuses_modes12([128, 128, 128])
+    assert px.tucker_fuses_modes12([40, 41, 42])
+    assert px.tucker_fuses_modes12([4096, 128])
+    assert px.tucker_fuses_modes12([3, 4, 5, 6])
+    assert not px.tucker_fuses_modes12([128])                      # one mode
+    assert not px.tucker_fuses_modes12([128, 129, 3])              # n2 > 128
+    assert not px.tucker_fuses_modes12([4097, 3])                  # n1 > 4096
+    assert not px.tucker_fuses_modes12([64, 64, 64], px.C128)      # complex data
+    assert not px.tucker_fuses_modes12([64, 64, 64], px.F64, "fp32")
+    assert not px.tucker_fuses_modes12([64, 64, 64], px.F64, "slice")
+    monkeypatch.setenv("EXPINT_FUSE12", "0")
+    assert not px.tucker_fuses_modes12([128, 128, 128])
+    monkeypatch.setenv("EXPINT_FUSE12", "1")
+    monkeypatch.setenv("EXPINT_TILE", "64x64")
+    assert not px.tucker_fuses_modes12([128, 128, 128])
+    out = ctypes.c_int(7)
+    n = (ctypes.c_int * 2)(4, 5)
+    assert B.lib.tucker_fuses_modes12(0, n, 0, 0, ctypes.byref(out)) == B.EINVAL
+    assert B.lib.tucker_fuses_modes12(2, n, 7, 0, ctypes.byref(out)) == B.EINVAL
+    assert B.lib.tucker_fuses_modes12(2, n, 0, 9, ctypes.byref(out)) == B.EINVAL
+    assert B.lib.tucker_fuses_modes12(2, n, 0, 0, None) == B.EINVAL
+    assert out.value == 7

@@ -50,6 +50,14 @@ def test_tucker_real(n):
     assert rel_inf(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("n", SHAPES)
+def test_tucker_real_single_mode_launches(n, monkeypatch):
+    """The same shapes with modes 1 and 2 as separate launches (EXPINT_FUSE12=0)."""
+    monkeypatch.setenv("EXPINT_FUSE12", "0")
+    got, ref = _run(n, seed=sum(n))
+    assert rel_inf(got, ref) <= TOL
+
+
 @pytest.mark.parametrize("n", [(5,), (5, 7, 3), (48, 48, 48), (33, 17), (96, 96, 96)])
 def test_tucker_complex(n):
     got, ref = _run(n, seed=3 + sum(n), cplx=True)
