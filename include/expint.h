@@ -103,6 +103,20 @@ int phi_setup(int n, const double* A, int lda, double tau, int ell_max,
 int phi_setup_z(int n, const double* A, int lda, double tau, int ell_max,
                 double* phi_out, int ldphi);
 
+/* Constructions of the phi matrices (section 3.1). */
+#define EXPINT_PHI_TAYLOR 0  /* scale by 2^s (||.||_1 <= 1/2), Taylor series eq. seriesdef, eq. squarephi */
+#define EXPINT_PHI_QUAD   1  /* the paper's: scale by 2^s (||.||_1 < 1); phi_0 = e^Y and, for l > 0,
+                                eq. phiquad on 8 Gauss-Legendre-Lobatto nodes of [0, 1] with the
+                                exponentials e^{(1-theta) Y} from diagonal Pade approximants; then
+                                eq. squarephi */
+
+/* phi_setup_ex -- phi_setup (dtype EXPINT_F64) or phi_setup_z (EXPINT_C128)
+ * with the construction chosen by method (EXPINT_PHI_*); same arguments,
+ * layout and errors, plus EINVAL for an unknown method or dtype.  Both
+ * constructions agree to FP64 rounding. */
+int phi_setup_ex(int n, const double* A, int lda, double tau, int ell_max, int method, int dtype,
+                 double* phi_out, int ldphi);
+
 /* ------------------------------------------------------------------------ */
 /* tucker_apply: W = alpha * (V x_1 M_1 x_2 ... x_d M_d) + beta * W          */
 /* ------------------------------------------------------------------------ */
@@ -171,6 +185,8 @@ typedef struct expint_problem {
                             complex data: FP64 or FP32 only); K u, g and the stage
                             combination stay FP64.  EXPINT_PREC_SLICED keeps int8
                             digits of every phi in the plan */
+  int phi_method;        /* construction of the phi matrices: EXPINT_PHI_TAYLOR (0) or
+                            EXPINT_PHI_QUAD */
 } expint_problem;
 
 /*

@@ -49,6 +49,7 @@ def _load():
     dp = ctypes.POINTER(c_double)
     lib.phi_setup.argtypes = [c_int, dp, c_int, c_double, c_int, dp, c_int]
     lib.phi_setup_z.argtypes = [c_int, dp, c_int, c_double, c_int, dp, c_int]
+    lib.phi_setup_ex.argtypes = [c_int, dp, c_int, c_double, c_int, c_int, c_int, dp, c_int]
     lib.tucker_apply.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
                                  c_double, c_double, c_int, c_int, c_void_p, c_size_t, c_void_p]
     lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_size_t)]
@@ -81,7 +82,7 @@ def _load():
 lib = _load()
 
 EXPORTED_SYMBOLS = (
-    "phi_setup", "phi_setup_z", "tucker_apply", "tucker_workspace_size", "tucker_fuses_modes12",
+    "phi_setup", "phi_setup_z", "phi_setup_ex", "tucker_apply", "tucker_workspace_size", "tucker_fuses_modes12",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_destroy", "expint_last_error",
     "expint_version",
@@ -103,6 +104,7 @@ class _Problem(ctypes.Structure):
         ("g_param2", ctypes.c_double),
         ("dtype", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("phi_method", ctypes.c_int),
     ]
 
 
@@ -130,8 +132,12 @@ def version() -> str:
 # phi_setup (host)
 # ---------------------------------------------------------------------------
 
-def phi_setup(A: np.ndarray, tau: float, ell_max: int) -> List[np.ndarray]:
-    """[phi_0(tau A), ..., phi_{ell_max}(tau A)] computed by the library on the host (FP64)."""
+PHI_METHODS = {"taylor": 0, "quad": 1}
+
+
+def phi_setup(A: np.ndarray, tau: float, ell_max: int, method: str = "taylor") -> List[np.ndarray]:
+    """[phi_0(tau A), ..., phi_{ell_max}(tau A)] computed by the library on the host (FP64).
+    method: "taylor" (scaled Taylor series) or "quad" (the paper's quadrature construction)."""
     A = np.asarray(A)
     n = A.shape[0]
     cplx = np.iscomplexobj(A)
@@ -141,8 +147,12 @@ def phi_setup(A: np.ndarray, tau: float, ell_max: int) -> List[np.ndarray]:
     src = Acm.reshape(-1, order="F").view(np.float64) if cplx else Acm.reshape(-1, order="F")
     src = np.ascontiguousarray(src)
     dst = out.view(np.float64)
-    fn = lib.phi_setup_z if cplx else lib.phi_setup
-    _check(fn(n, _dptr(src), n, float(tau), int(ell_max), _dptr(dst), n))
+    if method == "taylor":
+        fn = lib.phi_setup_z if cplx else lib.phi_setup
+        _check(fn(n, _dptr(src), n, float(tau), int(ell_max), _dptr(dst), n))
+    else:
+        _check(lib.phi_setup_ex(n, _dptr(src), n, float(tau), int(ell_max), PHI_METHODS[method],
+                                C128 if cplx else F64, _dptr(dst), n))
     return [out[l * n * n:(l + 1) * n * n].reshape((n, n), order="F").copy() for l in range(ell_max + 1)]
 
 
@@ -257,7 +267,8 @@ class Plan:
     """
 
     def __init__(self, A: Sequence[np.ndarray], tau: float, scheme: str, nonlin: str,
-                 g_param: float = 0.0, precision: str = "fp64", device="cuda", g_param2: float = 0.0):
+                 g_param: float = 0.0, precision: str = "fp64", device="cuda", g_param2: float = 0.0,
+                 phi_method: str = "taylor"):
         import torch
         A = [np.asarray(a) for a in A]
         cplx = any(np.iscomplexobj(a) for a in A) or nonlin == "cubic_nls"
@@ -282,6 +293,7 @@ class Plan:
         prob.g_param2 = float(g_param2)
         prob.dtype = self.dtype
         prob.precision = PRECISIONS[precision]
+        prob.phi_method = PHI_METHODS[phi_method]
         self._handle = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
             _check(lib.expint_plan_create(ctypes.byref(self._handle), ctypes.byref(prob)))

@@ -207,6 +207,16 @@ extern "C" int phi_setup_z(int n, const double* A, int lda, double tau, int ell_
   }
 }
 
+extern "C" int phi_setup_ex(int n, const double* A, int lda, double tau, int ell_max, int method, int dtype,
+                            double* phi_out, int ldphi) {
+  if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "phi_setup_ex: unknown dtype %d", dtype);
+  try {
+    return phi_setup_method(method, dtype == EXPINT_C128, n, A, lda, tau, ell_max, phi_out, ldphi);
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "phi_setup_ex: out of host memory");
+  }
+}
+
 // ---------------------------------------------------------------------------
 // tucker_apply
 // ---------------------------------------------------------------------------
@@ -567,6 +577,8 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if (prob->dtype != EXPINT_F64 && prob->dtype != EXPINT_C128)
     return set_error(EXPINT_EINVAL, "unknown dtype %d", prob->dtype);
   if (!valid_precision(prob->precision)) return set_error(EXPINT_EINVAL, "unknown precision %d", prob->precision);
+  if (prob->phi_method != EXPINT_PHI_TAYLOR && prob->phi_method != EXPINT_PHI_QUAD)
+    return set_error(EXPINT_EINVAL, "unknown phi construction %d", prob->phi_method);
   if ((prob->precision == EXPINT_PREC_BF16X3 || prob->precision == EXPINT_PREC_SLICED) && prob->dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "complex data supports FP64 or FP32 (complex64) contraction");
   if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
@@ -626,8 +638,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
       rc = set_error(EXPINT_ENOMEM, "host allocation for phi failed");
       break;
     }
-    rc = cplx ? phi_setup_complex(n, prob->A[mu], n, p->tau, hi, host.data(), n)
-              : phi_setup_real(n, prob->A[mu], n, p->tau, hi, host.data(), n);
+    rc = phi_setup_method(prob->phi_method, cplx, n, prob->A[mu], n, p->tau, hi, host.data(), n);
     for (int l = lo; l <= hi && rc == EXPINT_OK; ++l) {
       void* dptr = nullptr;
       if (hipMalloc(&dptr, bytes) != hipSuccess) {

@@ -13,6 +13,9 @@ int set_error(int code, const char* fmt, ...);
 
 int phi_setup_real(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
 int phi_setup_complex(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
+// phi_0..phi_ell_max of tau A by EXPINT_PHI_TAYLOR or EXPINT_PHI_QUAD (complex: interleaved)
+int phi_setup_method(int method, bool cplx, int n, const double* A, int lda, double tau, int ell_max, double* out,
+                     int ldo);
 // keep this thread's phi_setup calls on one host thread (callers that already parallelise)
 void phi_setup_single_threaded(bool on);
 

@@ -33,8 +33,9 @@ def _printed(n, scheme, k):
     raise KeyError((n, scheme))
 
 
-def _gpu(p, use_graph=True):
-    plan = px.Plan(p.A, p.tau, p.scheme, "adr_paper", g_param=p.g_params["eps"], g_param2=p.g_params["alpha"])
+def _gpu(p, use_graph=True, phi_method="taylor"):
+    plan = px.Plan(p.A, p.tau, p.scheme, "adr_paper", g_param=p.g_params["eps"], g_param2=p.g_params["alpha"],
+                   phi_method=phi_method)
     U = px.tensor_to_device(p.u0)
     if use_graph:
         s = torch.cuda.Stream()
@@ -60,6 +61,18 @@ def test_gpu_reproduces_printed_error(n, scheme, k):
     steps, printed = _printed(n, scheme, k)
     p = W.adr_paper(n, steps=steps, scheme=scheme)
     U = _gpu(p)
+    err = rel_inf(U, nonlinear.adr_exact(1.0, p.g_params["grids"]))
+    assert abs(err - printed) <= max(2e-9 * printed, 1e-14), (err, printed)
+
+
+@pytest.mark.parametrize("n,scheme,k", [((40, 41, 42), "etd2rk", 0), ((40, 41, 42), "exp_euler", 4),
+                                         ((80, 81, 82), "etd2rk", 4)])
+def test_gpu_reproduces_printed_error_with_the_papers_phi(n, scheme, k):
+    """The same runs with the phi matrices built as the paper builds them (eq. phiquad
+    on Gauss-Lobatto nodes, eq. squarephi)."""
+    steps, printed = _printed(n, scheme, k)
+    p = W.adr_paper(n, steps=steps, scheme=scheme)
+    U = _gpu(p, phi_method="quad")
     err = rel_inf(U, nonlinear.adr_exact(1.0, p.g_params["grids"]))
     assert abs(err - printed) <= max(2e-9 * printed, 1e-14), (err, printed)
 
