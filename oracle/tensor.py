@@ -86,3 +86,17 @@ def forloop_tucker(V: np.ndarray, Ms: Sequence[np.ndarray]) -> np.ndarray:
             acc += w
         out[i] = acc
     return out
+
+
+def tucker_entry(V: np.ndarray, Ms: Sequence[np.ndarray], i: Sequence[int]):
+    """One entry of the Tucker operator by eq. forloop:
+    sum_j M_1[i_1, j_1] ... M_d[i_d, j_d] V[j_1, ..., j_d], contracting mode 1
+    first (each step a library matrix-vector product over one index; the
+    column-stacked layout of the tensors makes every step a view).  Also returns
+    the same sum over absolute values, which bounds its rounding error."""
+    w, a = np.asarray(V), np.abs(V)
+    for mu in range(len(Ms)):
+        rest = w.shape[1:]
+        w = (Ms[mu][i[mu], :] @ w.reshape(w.shape[0], -1, order="F")).reshape(rest, order="F")
+        a = (np.abs(Ms[mu][i[mu], :]) @ a.reshape(a.shape[0], -1, order="F")).reshape(rest, order="F")
+    return w[()], a[()]

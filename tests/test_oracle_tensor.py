@@ -8,7 +8,7 @@ import pytest
 from scipy.linalg import expm
 
 from oracle.phi import phi_functions
-from oracle.tensor import (dense_kron_product, dense_kron_sum, forloop_tucker,
+from oracle.tensor import (dense_kron_product, dense_kron_sum, forloop_tucker, tucker_entry,
                            kron_sum_action, mode_product, tucker, unvec, vec)
 
 
@@ -121,3 +121,28 @@ def test_split_exact_when_operators_vanish():
         split = math.factorial(ell) ** 2 * dense_kron_product(
             [phi_functions(np.zeros((k, k)), ell)[ell] for k in (2, 3, 2)])
         assert np.allclose(split, np.eye(12) / math.factorial(ell), atol=1e-15)
+
+
+def test_tucker_entry_matches_forloop_and_tucker():
+    """Single entries (the full-size GPU tests sample them) against the element loop
+    eq. forloop on a tiny tensor and against the whole Tucker operator on a larger one,
+    real and complex; the absolute-value sum bounds the entry."""
+    rng = np.random.default_rng(11)
+    n = (3, 4, 2)
+    V = rng.standard_normal(n)
+    Ms = [rng.standard_normal((k, k)) for k in n]
+    ref = forloop_tucker(V, Ms)
+    for i in [(0, 0, 0), (2, 3, 1), (1, 2, 0)]:
+        e, a = tucker_entry(V, Ms, i)
+        assert abs(e - ref[i]) <= 1e-14 * a
+        assert a >= abs(ref[i])
+    n = (9, 7, 8, 5)
+    V = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Ms = [rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)) for k in n]
+    full = tucker(V, Ms)
+    for i in [(0, 0, 0, 0), (8, 6, 7, 4), (3, 1, 5, 2)]:
+        e, a = tucker_entry(V, Ms, i)
+        assert abs(e - full[i]) <= 1e-14 * a
+    # a transposed factor (M_2^T for M_2) is caught
+    e, a = tucker_entry(V, [Ms[0], Ms[1].T, Ms[2], Ms[3]], (3, 1, 5, 2))
+    assert abs(e - full[3, 1, 5, 2]) > 1e-6 * a
