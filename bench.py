@@ -277,7 +277,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(sharding is described in the design notes only).", file=sys.stderr)
         sys.exit(2)
     if args.workload in ("riccati64", "riccati64_ros"):

@@ -64,7 +64,7 @@ def etd2rk_step(U, t, tau, A, P1, P2, g):
 
 
 class Integrator:
-    """Constant-step driver: builds phi_l(tau A_mu) once (section 3.1 / 4.2), then steps."""
+    """Constant-step integrator: builds phi_l(tau A_mu) once (section 3.1 / 4.2), then steps."""
 
     def __init__(self, A_list: Sequence[np.ndarray], tau: float, scheme: str,
                  g: Callable, phis: Optional[List[List[np.ndarray]]] = None):
