@@ -269,7 +269,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "slice"],
                     help="contraction precision of the mu-mode products (state and phi stay FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=22.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -561,7 +561,7 @@ def cpu_baseline(p, plan, U0, budget_s):
     plan.run(Ug, k)
     torch.cuda.synchronize()
     err = rel_inf(px.tensor_from_device(Ug), U)
-    return {
+    out = {
         "value": p.N * k / total,
         "unit": "DOF-steps/s",
         "cores": threads,
@@ -571,6 +571,24 @@ def cpu_baseline(p, plan, U0, budget_s):
         "seconds": round(total, 3),
         "gpu_vs_oracle_rel_inf": err,
     }
+    # the same oracle on one thread, over a shorter sample (about a third of the budget)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            U1 = np.array(p.u0)
+            t = time.perf_counter()
+            U1 = integ.step(U1, 0.0)
+            one1 = time.perf_counter() - t
+            k1 = max(1, min(p.steps, int(math.ceil(budget_s / 3 / max(one1, 1e-6)))))
+            t = time.perf_counter()
+            for i in range(1, k1):
+                U1 = integ.step(U1, i * p.tau)
+            total1 = one1 + time.perf_counter() - t
+        out["single_thread"] = {"value": p.N * k1 / total1, "unit": "DOF-steps/s", "cores": 1,
+                                "sample": f"first {k1} of {p.steps} steps", "seconds": round(total1, 3)}
+    except ImportError:
+        pass
+    return out
 
 
 if __name__ == "__main__":
