@@ -330,6 +330,22 @@ def main():
     if not torch.isfinite(U).all():
         raise SystemExit("non-finite state after the timed region")
 
+    # five more regions of K steps from the same start, after the timed one, for
+    # the spread of the figure (the reported value is the timed region above)
+    U_timed = U.clone()
+    repeats = []
+    for _ in range(5):
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        with torch.cuda.stream(stream):
+            plan.run(U, args.steps, t0=0.0, use_graph=True, stream=stream)
+        r1.record(stream)
+        stream.synchronize()
+        repeats.append(r0.elapsed_time(r1) / max(args.steps, 1))
+
     if plan.fused:
         # the whole timed run is one launch of the fused small-problem kernel: its
         # duration is the event time of the timed region, its work the Tucker flops
@@ -375,6 +391,9 @@ def main():
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
                    "precision": args.precision, "graph": True},
         "wall_s_timed_region": wall,
+        "repeat_ms_per_step": [round(x, 5) for x in repeats],
+        "median_ms_per_step_of_repeats": round(sorted(repeats)[len(repeats) // 2], 5),
+        "repeats_bitwise_equal_to_timed_state": bool(torch.equal(U, U_timed)),
         "tucker_tflops_whole_step": round(step_tf, 3),
         "roofline": roofline,
     }
