@@ -263,7 +263,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 100; the paper's step count for adr_paper*)")
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=300,
+                    help="untimed steps before the timed region (default 300: about 30 ms at 128^3, which "
+                         "the clocks need to settle; with 20 the timed region ran 6%% slower than later repeats)")
     ap.add_argument("--workload", default="adr128")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "slice"],
