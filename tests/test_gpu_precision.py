@@ -30,8 +30,11 @@ def _rand(shape, seed):
     return np.random.default_rng(seed).uniform(-1, 1, size=shape)
 
 
+# (130, 129, 250) gives every mode 512 or more output tiles of the reduced-precision kernels
+# (a large grid next to the small ones)
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("n", [(7,), (33, 65), (40, 41, 42), (128, 128, 128), (17, 1, 70), (3, 4, 5, 6)])
+@pytest.mark.parametrize("n", [(7,), (33, 65), (40, 41, 42), (128, 128, 128), (17, 1, 70), (3, 4, 5, 6),
+                               (130, 129, 250)])
 def test_tucker_reduced_precision(prec, n):
     V = _rand(n, 1)
     Ms = [_rand((k, k), 2 + i) / np.sqrt(k) for i, k in enumerate(n)]
