@@ -43,7 +43,7 @@ def _load():
     # runtime, so device pointers and streams from torch are valid here.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_02327_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2304_02327_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     dp = ctypes.POINTER(c_double)

@@ -1,6 +1,6 @@
 """Build libexpint.so (HIP for gfx950) in-tree.
 
-Usage: python -m paper_2304_02327_amd.build  (or call build()).
+Usage: python paper_2304_02327_amd/build.py  (or call build()).
 Object files go to <repo>/_build/; the library lands next to this file.
 """
 
