@@ -1,13 +1,20 @@
 """Benchmark: direction-split exponential integrator steps on one MI355X.
 
-Default workload: 3-D advection-diffusion-reaction on 128^3, ETD2RK phisplit,
-FP64, tau = 2e-3 (A_mu = 0.02 D2 + beta_mu D1, g = u^2 (1 - u)).  A "step" is
-one full ETD2RK time step over the whole tensor (stage input with K u and g,
-two Tucker operators with the fused stage combinations), replayed from a HIP
-graph.  Inputs are resident in HBM before the timed region starts.
+Default workload: the precision sweep on 3-D diffusion-reaction, 384^3,
+ETD2RK phisplit, tau = 2e-3 (A_mu = 0.02 D2, g = u^2 (1 - u), u0 ~ U(0, 1)).
+A "step" is one full ETD2RK time step over the whole tensor (stage input with
+K u and g, two Tucker operators with the fused stage combinations), replayed
+from a HIP graph; inputs are resident in HBM before each timed region starts.
+The mu-mode contractions run in four precisions, each timed over the same K
+steps: FP32, split BF16 (bf16x3), exact slice (int8 digits) and FP64, which
+gives `value`.  Each reduced leg reports its time, its speed-up over FP64,
+its error against the FP64 run and against the CPU oracle, and its own
+roofline.
 
 Prints one JSON line with DOF-steps/s, the roofline of the dominant kernel
 (the FP64 MFMA mu-mode product) and the CPU oracle timed on the host.
+Other workloads: --workload adr128 | allen_cahn64 | nls192 | dr384 |
+riccati64 | riccati64_ros | adr_paper40 | adr_paper80.
 """
 
 from __future__ import annotations
@@ -76,36 +83,54 @@ def plan_kwargs(p):
     return {}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_modes12_adr128_hbm_traffic.md")
+# Committed rocprofv3 PMC summaries of the dominant kernel, per workload and
+# contraction precision.  Each lists the sources the kernel is compiled from and
+# their SHA-256; `traffic` is reported only while that hash matches the tree.
+TRAFFIC_FILES = {
+    ("adr128", "fp64"): "k_modes12_adr128_hbm_traffic.md",
+    ("dr384", "fp64"): "k_mode_product_dr384_hbm_traffic.md",
+    ("dr384", "fp32"): "k_mode_product_f32_dr384_hbm_traffic.md",
+    ("dr384", "bf16x3"): "k_mode_product_bf16x3_dr384_hbm_traffic.md",
+    ("dr384", "slice"): "k_sliced_dr384_hbm_traffic.md",
+}
 
 
-TRAFFIC_SOURCES = ("paper_2304_02327_amd/csrc/modes12.hip", "paper_2304_02327_amd/csrc/mode_product.hip",
-                   "paper_2304_02327_amd/csrc/tile_common.h",
-                   "paper_2304_02327_amd/csrc/device_common.h", "paper_2304_02327_amd/csrc/internal.h",
-                   "include/expint.h")
-
-
-def kernel_sources_sha256() -> str:
-    """SHA-256 over the sources the mu-mode product kernel is compiled from."""
+def sources_sha256(rels):
+    """SHA-256 over the named source files (paths relative to the repository), or None
+    if one of them is missing."""
     import hashlib
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in rels:
+        path = os.path.join(ROOT, rel)
+        if not os.path.isfile(path):
+            return None
         h.update(rel.encode())
-        h.update(open(os.path.join(ROOT, rel), "rb").read())
+        h.update(open(path, "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed PMC summary, or None when
-    the workload differs or the kernel's sources changed since the counters were taken."""
-    if workload != "adr128" or not os.path.exists(TRAFFIC_FILE):
-        return None
+def _summary_fields(path):
     fields = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if " = " in line:
             k, v = line.strip().split(" = ", 1)
             fields[k] = v
-    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+    return fields
+
+
+def measured_traffic(workload: str, precision: str = "fp64"):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary, or None when
+    there is none for this workload and precision or the kernel's sources changed since the
+    counters were taken."""
+    name = TRAFFIC_FILES.get((workload, precision))
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    fields = _summary_fields(path)
+    rels = [r.strip() for r in fields.get("kernel_sources", "").split(",") if r.strip()]
+    if not rels or fields.get("kernel_sources_sha256") != sources_sha256(rels):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -258,36 +283,143 @@ def bench_riccati(args, scheme="etd2rk"):
     print(json.dumps(result))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 100; the paper's step count for adr_paper*)")
-    ap.add_argument("--warmup", type=int, default=300,
-                    help="untimed steps before the timed region (default 300: about 30 ms at 128^3, which "
-                         "the clocks need to settle; with 20 the timed region ran 6%% slower than later repeats)")
-    ap.add_argument("--workload", default="adr128")
-    ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "slice"],
-                    help="contraction precision of the mu-mode products (state and phi stay FP64)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=22.0)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain device copy of 512 MiB five times (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        calibrate_copy()
-        return
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
-              "(sharding is described in the design notes only).", file=sys.stderr)
-        sys.exit(2)
-    if args.workload in ("riccati64", "riccati64_ros"):
-        if args.steps is None:
-            args.steps = 20
-        bench_riccati(args, "rosenbrock_euler" if args.workload == "riccati64_ros" else "etd2rk")
-        return
+SWEEP_PRECISIONS = ("fp32", "bf16x3", "slice", "fp64")  # FP64 last: its timed region gives `value`
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
+              "slice": "int8 digits x6/int32 acc (state f64)"}
+# the stated bound of each precision's error against the FP64 oracle (rel-inf, a few steps)
+PREC_BOUND = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "slice": 1e-10}
 
+
+def _event_ms(stream, fn):
+    """Time fn() with HIP events recorded on `stream` (the stream its kernels run on)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_steps(plan, U0, steps, warmup, stream, repeats=0):
+    """W untimed graph-replayed steps (including the one-time capture), then exactly
+    `steps` timed ones from U0 with HIP events on the plan's stream, bracketed by
+    device synchronisation; optional repeat regions for the spread.  Returns
+    (ms of the timed region, wall seconds, final state, repeat ms per step)."""
+    import torch
+    U = U0.clone()
+    with torch.cuda.stream(stream):
+        plan.run(U, warmup, t0=0.0, use_graph=True, stream=stream)
+    stream.synchronize()
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = _event_ms(stream, lambda: plan.run(U, steps, t0=0.0, use_graph=True, stream=stream))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    final = U.clone()
+    reps = []
+    for _ in range(repeats):
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        reps.append(_event_ms(stream, lambda: plan.run(U, steps, t0=0.0, use_graph=True, stream=stream))
+                    / max(steps, 1))
+    bitwise = bool(torch.equal(U, final)) if repeats else None
+    return ms, wall, final, reps, bitwise
+
+
+def bench_sweep(args):
+    """The precision sweep: 384^3 diffusion-reaction, ETD2RK, K steps in FP32, bf16x3,
+    exact slice and FP64 contraction; `value` is the FP64 leg."""
+    import numpy as np
+    import torch
+    import paper_2304_02327_amd as px
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = W.diffusion_reaction_3d(n=384)
+    if args.steps is None:
+        args.steps = p.steps
+    desc = ("precision sweep: 3-D diffusion-reaction 384^3, ETD2RK phisplit, tau=2e-3, "
+            "mu-mode contractions in FP64 vs FP32 vs split-BF16 (bf16x3) vs exact slice (int8 digits)")
+    U0 = px.tensor_to_device(p.u0, device=dev)
+    stream = torch.cuda.Stream()  # default priority
+    stream.wait_stream(torch.cuda.current_stream())
+    legs, finals = {}, {}
+    for prec in SWEEP_PRECISIONS:
+        t = time.perf_counter()
+        plan = px.Plan(p.A, p.tau, p.scheme, p.g, precision=prec)
+        setup_s = time.perf_counter() - t
+        ms, wall, final, reps, bitwise = time_steps(plan, U0, args.steps, args.warmup, stream,
+                                                    repeats=5 if prec == "fp64" else 0)
+        if not plan.check_finite(final, stream=stream):
+            raise SystemExit(f"non-finite state after the timed region ({prec})")
+        finals[prec] = final
+        leg = {"ms_per_step": ms / args.steps, "value": p.N * args.steps / (ms / 1e3), "unit": "DOF-steps/s",
+               "dtype": PREC_DTYPE[prec], "wall_s_timed_region": wall, "plan_setup_s": round(setup_s, 3),
+               "stated_bound_rel_inf": PREC_BOUND[prec],
+               "roofline": tucker_roofline(args, p, px, dev, stream, U0, prec, "dr384")}
+        if reps:
+            leg["repeat_ms_per_step"] = [round(x, 5) for x in reps]
+            leg["median_ms_per_step_of_repeats"] = round(sorted(reps)[len(reps) // 2], 5)
+            leg["repeats_bitwise_equal_to_timed_state"] = bitwise
+        legs[prec] = leg
+        plan.close()
+    fp = legs["fp64"]
+    ref = finals["fp64"]
+    scale = ref.abs().max().item()
+    reduced = {}
+    for prec in SWEEP_PRECISIONS[:-1]:
+        leg = legs[prec]
+        leg["speedup_vs_fp64"] = fp["ms_per_step"] / leg["ms_per_step"]
+        leg[f"rel_inf_vs_fp64_after_{args.steps}_steps"] = (finals[prec] - ref).abs().max().item() / scale
+        reduced[prec] = leg
+    result = {
+        "metric": METRIC,
+        "value": fp["value"],
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau, "graph": True,
+                   "value_from": "the FP64 leg; the other legs are in precision_legs"},
+        "wall_s_timed_region": fp["wall_s_timed_region"],
+        "repeat_ms_per_step": fp["repeat_ms_per_step"],
+        "median_ms_per_step_of_repeats": fp["median_ms_per_step_of_repeats"],
+        "repeats_bitwise_equal_to_timed_state": fp["repeats_bitwise_equal_to_timed_state"],
+        "tucker_tflops_whole_step": round(tucker_flops_per_step(p) * args.steps / (fp["ms_per_step"] * args.steps
+                                                                                   / 1e3) / 1e12, 3),
+        "roofline": fp["roofline"],
+        "precision_legs": reduced,
+    }
+    if not args.no_cpu_baseline:
+        base, oracle_state, k = oracle_sample(p, args.cpu_seconds)
+        # every leg against the oracle after the same k steps (direct launches)
+        for prec in SWEEP_PRECISIONS:
+            plan = px.Plan(p.A, p.tau, p.scheme, p.g, precision=prec)
+            Ug = U0.clone()
+            plan.run(Ug, k)
+            torch.cuda.synchronize()
+            err = float(np.abs(px.tensor_from_device(Ug) - oracle_state).max() / np.abs(oracle_state).max())
+            plan.close()
+            if prec == "fp64":
+                base["gpu_vs_oracle_rel_inf"] = err
+            else:
+                reduced[prec][f"rel_inf_vs_oracle_after_{k}_steps"] = err
+                reduced[prec]["within_stated_bound"] = bool(err <= PREC_BOUND[prec])
+        result["cpu_baseline"] = base
+    print(json.dumps(result))
+
+
+def bench_single(args):
+    """One workload in one contraction precision."""
     import numpy as np
     import torch
     import paper_2304_02327_amd as px
@@ -303,50 +435,13 @@ def main():
     U0 = px.tensor_to_device(p.u0, device=dev)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    U = U0.clone()
     stream = torch.cuda.Stream()  # default priority
     stream.wait_stream(torch.cuda.current_stream())
-
-    # warmup (includes the one-time graph capture)
-    with torch.cuda.stream(stream):
-        plan.run(U, args.warmup, t0=0.0, use_graph=True, stream=stream)
-    stream.synchronize()
-    U.copy_(U0)
-    torch.cuda.synchronize()
-
-    # timed region: exactly K graph-replayed steps
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    with torch.cuda.stream(stream):
-        plan.run(U, args.steps, t0=0.0, use_graph=True, stream=stream)
-    ev1.record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms, wall, U, repeats, bitwise = time_steps(plan, U0, args.steps, args.warmup, stream, repeats=5)
     ms_per_step = gpu_ms / max(args.steps, 1)
     value = p.N * args.steps / (gpu_ms / 1e3)
-    if not torch.isfinite(U).all():
+    if not plan.check_finite(U, stream=stream):
         raise SystemExit("non-finite state after the timed region")
-
-    # five more regions of K steps from the same start, after the timed one, for
-    # the spread of the figure (the reported value is the timed region above)
-    U_timed = U.clone()
-    repeats = []
-    for _ in range(5):
-        U.copy_(U0)
-        torch.cuda.synchronize()
-        r0 = torch.cuda.Event(enable_timing=True)
-        r1 = torch.cuda.Event(enable_timing=True)
-        r0.record(stream)
-        with torch.cuda.stream(stream):
-            plan.run(U, args.steps, t0=0.0, use_graph=True, stream=stream)
-        r1.record(stream)
-        stream.synchronize()
-        repeats.append(r0.elapsed_time(r1) / max(args.steps, 1))
 
     if plan.fused:
         # the whole timed run is one launch of the fused small-problem kernel: its
@@ -371,7 +466,7 @@ def main():
             "us_per_step": round(avg_launch_s * 1e6 / max(args.steps, 1), 3),
         }
     else:
-        roofline = tucker_roofline(args, p, px, dev, stream, U0)
+        roofline = tucker_roofline(args, p, px, dev, stream, U0, args.precision, args.workload)
     step_tf = tucker_flops_per_step(p) * args.steps / (gpu_ms / 1e3) / 1e12
 
     result = {
@@ -386,16 +481,14 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("c128" if p.is_complex else "f64") if args.precision == "fp64" else
-                 ("c64 (state c128)" if p.is_complex else
-                  {"fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
-                   "slice": "int8 digits x6/int32 acc (state f64)"}[args.precision]),
+                 ("c64 (state c128)" if p.is_complex else PREC_DTYPE[args.precision]),
         "data": "synthetic",
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
                    "precision": args.precision, "graph": True},
         "wall_s_timed_region": wall,
         "repeat_ms_per_step": [round(x, 5) for x in repeats],
         "median_ms_per_step_of_repeats": round(sorted(repeats)[len(repeats) // 2], 5),
-        "repeats_bitwise_equal_to_timed_state": bool(torch.equal(U, U_timed)),
+        "repeats_bitwise_equal_to_timed_state": bitwise,
         "tucker_tflops_whole_step": round(step_tf, 3),
         "roofline": roofline,
     }
@@ -438,12 +531,74 @@ def main():
             worst = max(worst, abs(lhs - rhs) / rhs)
         result["mass_identity_max_rel_residual_10_steps"] = worst
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(p, plan, U0, args.cpu_seconds)
+        base, oracle_state, k = oracle_sample(p, args.cpu_seconds)
+        Ug = U0.clone()
+        plan.run(Ug, k)
+        torch.cuda.synchronize()
+        base["gpu_vs_oracle_rel_inf"] = float(np.abs(px.tensor_from_device(Ug) - oracle_state).max()
+                                              / np.abs(oracle_state).max())
+        result["cpu_baseline"] = base
     plan.close()
     print(json.dumps(result))
 
 
-def tucker_roofline(args, p, px, dev, stream, U0):
+def bench_kernel_only(args):
+    """Only the roofline timing loop of one workload and precision (tucker_apply with the
+    step's shapes): a short program for rocprofv3 PMC passes."""
+    import torch
+    import paper_2304_02327_amd as px
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p, _ = make_workload(args.workload)
+    U0 = px.tensor_to_device(p.u0, device=dev)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    r = tucker_roofline(args, p, px, dev, stream, U0, args.precision, args.workload)
+    print(json.dumps({"kernel_only": args.workload, "precision": args.precision,
+                      "avg_launch_us": r["avg_launch_us"], "kernel_reps": args.kernel_reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's own count, 20 for the 384^3 sweep, 100 for "
+                         "adr128, the paper's step count for adr_paper*)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed graph-replayed steps before each timed region")
+    ap.add_argument("--workload", default="dr384_sweep")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "slice"],
+                    help="contraction precision of the mu-mode products for a single workload "
+                         "(state and phi stay FP64); the default sweep runs all four")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=22.0)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only time the dominant kernel of --workload/--precision (for PMC passes)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 512 MiB five times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(sharding is described in the design notes only).", file=sys.stderr)
+        sys.exit(2)
+    if args.kernel_only:
+        bench_kernel_only(args)
+        return
+    if args.workload in ("riccati64", "riccati64_ros"):
+        if args.steps is None:
+            args.steps = 20
+        bench_riccati(args, "rosenbrock_euler" if args.workload == "riccati64_ros" else "etd2rk")
+        return
+    if args.workload == "dr384_sweep":
+        bench_sweep(args)
+        return
+    bench_single(args)
+
+
+def tucker_roofline(args, p, px, dev, stream, U0, precision, workload):
     """Roofline of the dominant kernel: the fused launch of modes 1 and 2 where the
     Tucker operator uses it (FP64 real data, n_2 <= 128), else the mu-mode product.
     tucker_apply with the shapes and launch configuration of the step (the phi_1
@@ -454,24 +609,20 @@ def tucker_roofline(args, p, px, dev, stream, U0):
     Vk = U0.clone()
     Wk = torch.empty_like(Vk)
     prec_code = {"fp64": px.PREC_FP64, "fp32": px.PREC_FP32, "bf16x3": px.PREC_BF16X3,
-                 "slice": px.PREC_SLICED}[args.precision]
+                 "slice": px.PREC_SLICED}[precision]
     ws = torch.empty(max(px.tucker_workspace_size(p.n, px.C128 if p.is_complex else px.F64, prec_code), 16),
                      dtype=torch.uint8, device=dev)
+
     def time_per_call(mats):
         with torch.cuda.stream(stream):
             for _ in range(3):
                 px.tucker_apply(mats, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
-            k0 = torch.cuda.Event(enable_timing=True)
-            k1 = torch.cuda.Event(enable_timing=True)
-            k0.record(stream)
-            for _ in range(args.kernel_reps):
-                px.tucker_apply(mats, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
-            k1.record(stream)
-        stream.synchronize()
-        return k0.elapsed_time(k1) / 1e3 / args.kernel_reps
+        ms = _event_ms(stream, lambda: [px.tucker_apply(mats, Vk, Wk, ws=ws, stream=stream, precision=prec_code)
+                                        for _ in range(args.kernel_reps)])
+        return ms / 1e3 / args.kernel_reps
 
     dt_code = px.C128 if p.is_complex else px.F64
-    fused12 = args.precision == "fp64" and px.tucker_fuses_modes12(p.n, dt_code, prec_code)
+    fused12 = precision == "fp64" and px.tucker_fuses_modes12(p.n, dt_code, prec_code)
     esz = 16 if p.is_complex else 8
     if fused12:
         # the dominant kernel is the fused launch of modes 1 and 2 (M_3.. = identity:
@@ -482,6 +633,7 @@ def tucker_roofline(args, p, px, dev, stream, U0):
         avg_launch_s = time_per_call(Ms) / p.d
         flops_per_launch = sum((8 if p.is_complex else 2) * p.N * nm for nm in p.n) / p.d
     achieved_tf = flops_per_launch / avg_launch_s / 1e12
+    traffic = measured_traffic(workload, precision)
     if fused12:
         alg_bytes = 2 * esz * p.N + esz * (p.n[0] ** 2 + p.n[1] ** 2)
         roofline = {
@@ -491,7 +643,7 @@ def tucker_roofline(args, p, px, dev, stream, U0):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
-            "traffic": measured_traffic(args.workload),
+            "traffic": traffic,
         }
         if p.d > 2:  # the remaining single-mode launches, timed alone beside it
             rest_s = time_per_call([None, None] + list(Ms[2:]))
@@ -500,7 +652,7 @@ def tucker_roofline(args, p, px, dev, stream, U0):
                 "k_mode_product (modes 3..d, one launch each)": {
                     "avg_launch_us": round(rest_s / (p.d - 2) * 1e6, 3),
                     "achieved_tflops": round(rest_flops / rest_s / 1e12, 3)}}
-    elif args.precision == "fp64":
+    elif precision == "fp64":
         alg_bytes = 2 * esz * p.N
         roofline = {
             "kernel": "k_mode_product (FP64 MFMA mu-mode product)",
@@ -509,16 +661,16 @@ def tucker_roofline(args, p, px, dev, stream, U0):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
-            "traffic": measured_traffic(args.workload),
+            "traffic": traffic,
         }
-    elif args.precision == "slice":
-        # one mode of tucker_apply: digits of M (n^2) and of the tensor (read 8 B, write
-        # 6 B per element), then the int8 GEMM (read 6 B, write 8 B per element)
+    elif precision == "slice":
+        # one mode of tucker_apply: digits of the tensor (read 8 B, write 6 B per element),
+        # then the int8 GEMM (read 6 B, write 8 B per element); the digits of M are small
         alg_bytes = 28 * p.N
         hw_tops = SLICE_PRODUCTS * flops_per_launch / avg_launch_s / 1e12
         roofline = {"kernel": "k_slice_* + k_sliced_gemm (exact-slice mu-mode product, int8 MFMA)",
                     "bound": "mfma", "achieved": round(hw_tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                    "frac": round(hw_tops / PEAK_INT8_TOPS, 4), "traffic": None,
+                    "frac": round(hw_tops / PEAK_INT8_TOPS, 4), "traffic": traffic,
                     "algorithmic_tflops_fp64_equivalent": round(achieved_tf, 3),
                     "hardware_op_multiplier": SLICE_PRODUCTS}
     else:
@@ -527,19 +679,20 @@ def tucker_roofline(args, p, px, dev, stream, U0):
         tot = (12 + 8 * (p.d - 2) + 12) if p.d >= 2 else 16
         alg_bytes = tot * p.N / p.d
         gbs = alg_bytes / avg_launch_s / 1e9
-        hw_mult = 1 if args.precision == "fp32" else 3
-        peak_c = PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_BF16_TFLOPS
+        hw_mult = 1 if precision == "fp32" else 3
+        peak_c = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_BF16_TFLOPS
         intensity = hw_mult * flops_per_launch / alg_bytes
         ridge = peak_c * 1e12 / (PEAK_HBM_GBS * 1e9)
+        kname = "k_mode_product_f32" if precision == "fp32" else "k_mode_product_bf16x3"
         if intensity < ridge:
-            roofline = {"kernel": f"k_mode_product_{args.precision} ({args.precision} mu-mode product)",
+            roofline = {"kernel": f"{kname} ({precision} mu-mode product)",
                         "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic}
         else:
             hw_tf = hw_mult * achieved_tf
-            roofline = {"kernel": f"k_mode_product_{args.precision} ({args.precision} mu-mode product)",
+            roofline = {"kernel": f"{kname} ({precision} mu-mode product)",
                         "bound": "mfma", "achieved": round(hw_tf, 3), "peak": peak_c, "unit": "TFLOP/s",
-                        "frac": round(hw_tf / peak_c, 4), "traffic": None}
+                        "frac": round(hw_tf / peak_c, 4), "traffic": traffic}
         roofline["algorithmic_tflops_fp64_equivalent"] = round(achieved_tf, 3)
         roofline["hardware_flop_multiplier"] = hw_mult
     roofline.update({
@@ -551,14 +704,12 @@ def tucker_roofline(args, p, px, dev, stream, U0):
     return roofline
 
 
-def cpu_baseline(p, plan, U0, budget_s):
-    """The CPU FP64 oracle, timed on the host on a bounded sample of the same workload;
-    its state after the sample is also compared with the GPU's after as many steps."""
+def oracle_sample(p, budget_s):
+    """The CPU FP64 oracle, timed on the host on a bounded sample of the same workload
+    (its first k steps, k chosen for about budget_s seconds); returns the cpu_baseline
+    record, the oracle's state after k steps and k."""
     import numpy as np
-    import torch
-    import paper_2304_02327_amd as px
     from oracle import schemes
-    from oracle.norms import rel_inf
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -575,13 +726,7 @@ def cpu_baseline(p, plan, U0, budget_s):
     t = time.perf_counter()
     for i in range(1, k):
         U = integ.step(U, i * p.tau)
-    rest = time.perf_counter() - t
-    total = one + rest
-    # the GPU state after the same k steps (direct launches)
-    Ug = U0.clone()
-    plan.run(Ug, k)
-    torch.cuda.synchronize()
-    err = rel_inf(px.tensor_from_device(Ug), U)
+    total = one + time.perf_counter() - t
     out = {
         "value": p.N * k / total,
         "unit": "DOF-steps/s",
@@ -590,30 +735,28 @@ def cpu_baseline(p, plan, U0, budget_s):
         "sample": f"first {k} of {p.steps} steps of the same workload (oracle phi setup "
                   f"{setup_s:.2f} s excluded); host {os.cpu_count()} logical CPUs",
         "seconds": round(total, 3),
-        "gpu_vs_oracle_rel_inf": err,
     }
-    # the same oracle on one thread, over a shorter sample (about a third of the budget)
+    # the same oracle on one thread, over a shorter sample (about a third of the budget),
+    # where one step fits in it
     try:
         from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):
-            U1 = np.array(p.u0)
-            t = time.perf_counter()
-            U1 = integ.step(U1, 0.0)
-            one1 = time.perf_counter() - t
-            k1 = max(1, min(p.steps, int(math.ceil(budget_s / 3 / max(one1, 1e-6)))))
-            t = time.perf_counter()
-            for i in range(1, k1):
-                U1 = integ.step(U1, i * p.tau)
-            total1 = one1 + time.perf_counter() - t
-        out["single_thread"] = {"value": p.N * k1 / total1, "unit": "DOF-steps/s", "cores": 1,
-                                "sample": f"first {k1} of {p.steps} steps", "seconds": round(total1, 3)}
+        if one * threads <= budget_s / 3:
+            with threadpool_limits(limits=1):
+                U1 = np.array(p.u0)
+                t = time.perf_counter()
+                U1 = integ.step(U1, 0.0)
+                one1 = time.perf_counter() - t
+                k1 = max(1, min(p.steps, int(math.ceil(budget_s / 3 / max(one1, 1e-6)))))
+                t = time.perf_counter()
+                for i in range(1, k1):
+                    U1 = integ.step(U1, i * p.tau)
+                total1 = one1 + time.perf_counter() - t
+            out["single_thread"] = {"value": p.N * k1 / total1, "unit": "DOF-steps/s", "cores": 1,
+                                    "sample": f"first {k1} of {p.steps} steps", "seconds": round(total1, 3)}
     except ImportError:
         pass
-    return out
+    return out, U, k
 
 
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "--kernel-sources-sha256":
-        print(kernel_sources_sha256())
-    else:
-        main()
+    main()

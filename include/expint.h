@@ -40,7 +40,9 @@ extern "C" {
 #define EXPINT_ENOMEM     -2  /* host or device allocation failed (plan creation only) */
 #define EXPINT_EHIP       -3  /* a HIP runtime call failed */
 #define EXPINT_ENOTSUP    -4  /* valid but unsupported combination */
-#define EXPINT_ENUMERIC   -5  /* non-finite input to phi_setup */
+#define EXPINT_ENUMERIC   -5  /* non-finite input to phi_setup; a Rosenbrock-Euler phi_1 that needed more
+                                 squarings than its plan provides (expint_batch_status) */
+#define EXPINT_ENONFINITE -6  /* a state holds inf or nan (expint_plan_check_finite, expint_batch_status) */
 
 /* element types of U / V / W */
 #define EXPINT_F64   0    /* double */
@@ -237,6 +239,17 @@ int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
  * small-problem launch described at expint_run, else 0.  Errors: EINVAL. */
 int expint_plan_is_fused(const expint_plan* plan, int* fused);
 
+/*
+ * expint_plan_check_finite -- whether the state U (device, the plan's layout and
+ * element type) holds only finite values.  Enqueues one read of U on `stream`,
+ * waits for the stream and returns EXPINT_OK, or EXPINT_ENONFINITE if an entry
+ * (a real or imaginary part) is inf or nan.  Intended after expint_run /
+ * expint_step, whose kernels do not test their results.  Uses one device int
+ * of the plan: concurrent checks with the same plan race.
+ * Errors: EINVAL (NULL plan or U, misaligned U), EHIP.
+ */
+int expint_plan_check_finite(expint_plan* plan, const void* U, void* stream);
+
 /* expint_plan_destroy -- frees the plan's device memory and graph (NULL is a no-op).
  * The caller must make sure no enqueued work still uses the plan. */
 void expint_plan_destroy(expint_plan* plan);
@@ -280,9 +293,11 @@ int expint_riccati_plan_create(expint_batch_plan** plan, int count, const int* n
  * at every step in FP64: scaling by the even power of two that brings the
  * 1-norm to <= 1/2, the Taylor series of degree 13 by Horner (eq. seriesdef),
  * and the squaring recurrence eq. squarephi.  The number of squaring phases
- * per step is fixed at creation: the count ||tau A_mu||_1 needs plus 4; a
- * Jacobian direction needing more is squared only that many times and loses
- * accuracy.  Errors as expint_riccati_plan_create, and ENOTSUP for another scheme.
+ * per step is fixed at creation: the count ||tau A_mu||_1 needs plus 4.  A
+ * Jacobian direction that needs more (its Taylor series would be evaluated
+ * outside ||Y||_1 <= 1/2) is squared only that many times, and its step sets a
+ * device flag that expint_batch_status reports as EXPINT_ENUMERIC.
+ * Errors as expint_riccati_plan_create, and ENOTSUP for another scheme.
  */
 int expint_riccati_plan_create_ex(expint_batch_plan** plan, int count, const int* n1, const int* n2,
                                   const double* const* A1, const double* const* A2, const double* B,
@@ -303,6 +318,21 @@ int expint_batch_workspace_size(const expint_batch_plan* plan, size_t* bytes);
  */
 int expint_batch_step(expint_batch_plan* plan, double* U, void* ws, void* stream);
 int expint_batch_run(expint_batch_plan* plan, double* U, int nsteps, int use_graph, void* ws, void* stream);
+
+/*
+ * expint_batch_status -- waits for `stream`, then reports what the steps
+ * enqueued since the previous call found, and clears it:
+ *   EXPINT_ENUMERIC   a Rosenbrock-Euler Jacobian direction needed more
+ *                     squarings (section 3.1 scaling, eq. squarephi) than the
+ *                     plan provides, so its phi_1 is inaccurate;
+ *   EXPINT_ENONFINITE U (device packed state, optional: NULL skips the check)
+ *                     holds inf or nan, or a Jacobian direction had a
+ *                     non-finite 1-norm;
+ *   EXPINT_OK         neither.
+ * ENUMERIC is reported before ENONFINITE when both hold.  Synchronous.
+ * Errors: EINVAL (NULL plan, misaligned U), EHIP.
+ */
+int expint_batch_status(expint_batch_plan* plan, const double* U, void* stream);
 
 /* expint_batch_plan_destroy -- frees the plan (NULL is a no-op). */
 void expint_batch_plan_destroy(expint_batch_plan* plan);

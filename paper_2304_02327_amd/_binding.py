@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libexpint.so")
 
 # status codes, dtypes, precisions, schemes, nonlinearities (include/expint.h)
-OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENUMERIC, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 F64, C128 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_SLICED = 0, 1, 2, 3
 ROSENBROCK_EULER = 4  # batched Riccati plans only
@@ -60,6 +60,8 @@ def _load():
     lib.expint_step.argtypes = [c_void_p, c_void_p, c_double, c_void_p, c_void_p]
     lib.expint_run.argtypes = [c_void_p, c_void_p, c_double, c_int, c_int, c_void_p, c_void_p]
     lib.expint_plan_is_fused.argtypes = [c_void_p, ctypes.POINTER(c_int)]
+    lib.expint_plan_check_finite.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.expint_batch_status.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.expint_plan_destroy.argtypes = [c_void_p]
     lib.expint_plan_destroy.restype = None
     lib.expint_riccati_plan_create.argtypes = [ctypes.POINTER(c_void_p), c_int, ctypes.POINTER(c_int),
@@ -84,11 +86,12 @@ lib = _load()
 EXPORTED_SYMBOLS = (
     "phi_setup", "phi_setup_z", "phi_setup_ex", "tucker_apply", "tucker_workspace_size", "tucker_fuses_modes12",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
-    "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_destroy", "expint_last_error",
+    "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_check_finite", "expint_plan_destroy",
+    "expint_last_error",
     "expint_version",
     "expint_riccati_plan_create", "expint_riccati_plan_create_ex", "expint_batch_state_size",
     "expint_batch_workspace_size",
-    "expint_batch_step", "expint_batch_run", "expint_batch_plan_destroy",
+    "expint_batch_step", "expint_batch_run", "expint_batch_status", "expint_batch_plan_destroy",
 )
 
 
@@ -330,6 +333,15 @@ class Plan:
                               self.ws.data_ptr(), _stream_handle(stream)))
         return U
 
+    def check_finite(self, U, stream=None) -> bool:
+        """True if every entry of U is finite (waits for the stream)."""
+        self._check_state(U)
+        rc = lib.expint_plan_check_finite(self._handle, U.data_ptr(), _stream_handle(stream))
+        if rc == ENONFINITE:
+            return False
+        _check(rc)
+        return True
+
     def close(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:
             lib.expint_plan_destroy(self._handle)
@@ -419,6 +431,18 @@ class RiccatiBatch:
         _check(lib.expint_batch_run(self._handle, U.data_ptr(), int(nsteps), 1 if use_graph else 0,
                                     self.ws.data_ptr(), _stream_handle(stream)))
         return U
+
+    def status(self, U=None, stream=None) -> int:
+        """What the steps since the last call found (waits for the stream): OK,
+        ENUMERIC (a phi_1 needed more squarings than the plan has) or ENONFINITE
+        (U, if given, or a Jacobian direction holds inf / nan)."""
+        if U is not None:
+            self._check_state(U)
+        rc = lib.expint_batch_status(self._handle, U.data_ptr() if U is not None else None,
+                                     _stream_handle(stream))
+        if rc not in (OK, ENUMERIC, ENONFINITE):
+            _check(rc)
+        return rc
 
     def close(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

@@ -233,6 +233,25 @@ static int validate_shape(int d, const int* n, long* N) {
   return EXPINT_OK;
 }
 
+// Operand limits of the kernels, checked before anything is enqueued: every
+// mu-mode product addresses its operands with 32-bit buffer offsets (below
+// 2 GiB per tensor), and the exact-slice digits need n_mu <= 65535 and each
+// digit plane (fibres x padded length) below 2^31 bytes.
+static int check_operand_limits(int d, const int* n, long N, int dtype, int precision) {
+  const size_t bytes = (size_t)N * elem_size(dtype);
+  if (bytes >= (1ull << 31))
+    return set_error(EXPINT_ENOTSUP, "a tensor of %zu bytes exceeds the 2 GiB limit of one mu-mode product operand",
+                     bytes);
+  if (precision == EXPINT_PREC_SLICED)
+    for (int mu = 0; mu < d; ++mu) {
+      if (n[mu] > 65535) return set_error(EXPINT_ENOTSUP, "exact-slice precision: n[%d] = %d exceeds 65535", mu, n[mu]);
+      const size_t plane = (size_t)(N / n[mu]) * (size_t)slice_kpad(n[mu]);
+      if (plane >= (1ull << 31))
+        return set_error(EXPINT_ENOTSUP, "exact-slice precision: digit plane of mode %d exceeds 2 GiB", mu + 1);
+    }
+  return EXPINT_OK;
+}
+
 // Workspace layout of tucker_apply: FP64 / FP32 / BF16X3 use up to two
 // ping-pong tensors of N elements; the exact-slice chain uses one FP64 tensor,
 // the digit buffer of the largest mode and the digits of every M.
@@ -281,6 +300,7 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "tucker_apply: unknown precision %d", precision);
   if ((precision == EXPINT_PREC_BF16X3 || precision == EXPINT_PREC_SLICED) && dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "tucker_apply: complex data supports FP64 or FP32 (complex64) contraction");
+  TRY(check_operand_limits(d, n, N, dtype, precision));
   if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
   if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
   if (!aligned16(V) || !aligned16(W)) return set_error(EXPINT_EINVAL, "tucker_apply: V and W must be 16-byte aligned");
@@ -342,6 +362,7 @@ struct expint_plan {
   double* d_clock = nullptr;
   bool timedep = false;
   bool small = false;                // whole runs in one fused launch (small 2-D FP64 problems)
+  int* d_flag = nullptr;             // device int of expint_plan_check_finite
   // cached graph of one step
   hipGraphExec_t gexec = nullptr;
   const void* g_U = nullptr;
@@ -384,6 +405,7 @@ void free_plan_memory(expint_plan* p) {
   }
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->d_clock) (void)hipFree(p->d_clock);
+  if (p->d_flag) (void)hipFree(p->d_flag);
 }
 
 int scheme_phi_range(int scheme, int* lo, int* hi) {
@@ -582,6 +604,7 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
   if ((prob->precision == EXPINT_PREC_BF16X3 || prob->precision == EXPINT_PREC_SLICED) && prob->dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "complex data supports FP64 or FP32 (complex64) contraction");
   if (!std::isfinite(prob->tau)) return set_error(EXPINT_EINVAL, "tau is not finite");
+  TRY(check_operand_limits(prob->d, prob->n, N, prob->dtype, prob->precision));
   const bool cplx = prob->dtype == EXPINT_C128;
   if (cplx && prob->nonlin != EXPINT_G_NONE && prob->nonlin != EXPINT_G_CUBIC_NLS)
     return set_error(EXPINT_ENOTSUP, "complex data supports g = NONE or CUBIC_NLS");
@@ -676,7 +699,13 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
       const int w = cplx ? 2 : 1;
       const double* A = prob->A[mu];
       if (all_tri) {
-        std::vector<double> c((size_t)3 * n * w, 0.0);
+        std::vector<double> c;
+        try {
+          c.assign((size_t)3 * n * w, 0.0);
+        } catch (const std::bad_alloc&) {
+          rc = set_error(EXPINT_ENOMEM, "host allocation for the stencil failed");
+          break;
+        }
         auto put = [&](int slot, int i, int row, int col) {
           for (int k = 0; k < w; ++k) c[((size_t)slot * n + i) * w + k] = A[((size_t)row + (size_t)n * col) * w + k];
         };
@@ -737,6 +766,12 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
       p->gt.clock = p->d_clock;
     }
   }
+  if (rc == EXPINT_OK) {
+    if (hipMalloc(&p->d_flag, sizeof(int)) != hipSuccess)
+      rc = set_error(EXPINT_ENOMEM, "device allocation for the status flag failed");
+    else if (hipMemset(p->d_flag, 0, sizeof(int)) != hipSuccess)
+      rc = set_error(EXPINT_EHIP, "status flag initialisation failed");
+  }
   if (rc != EXPINT_OK) {
     free_plan_memory(p);
     delete p;
@@ -767,13 +802,27 @@ extern "C" int expint_plan_set_phi(expint_plan* p, int mu, int ell, const double
     return set_error(EXPINT_EINVAL, "phi_%d is not used by this scheme", ell);
   const int n = p->n[mu];
   const size_t bytes = (size_t)n * n * elem_size(p->dtype);
-  if (!p->phi_owner[mu][ell]) {
-    // this direction shared another direction's matrix: give it its own copy
+  // Directions with equal A share one device matrix.  Only direction mu
+  // changes: if any other direction still points at mu's matrix, mu moves to
+  // a fresh allocation (an owner hands its old matrix to the first sharer), so
+  // the sharers keep the matrix, and the digits, they had.
+  bool shared = false;
+  for (int nu = 0; nu < p->d; ++nu)
+    if (nu != mu && p->phi[nu][ell] == p->phi[mu][ell]) shared = true;
+  if (shared) {
     void* dptr = nullptr;
     if (hipMalloc(&dptr, bytes) != hipSuccess) return set_error(EXPINT_ENOMEM, "device allocation failed");
+    void* old = p->phi[mu][ell];
+    if (p->phi_owner[mu][ell]) {
+      for (int nu = 0; nu < p->d; ++nu)
+        if (nu != mu && p->phi[nu][ell] == old) {
+          p->phi_owner[nu][ell] = true;
+          break;
+        }
+    }
     p->phi[mu][ell] = dptr;
     p->phi_owner[mu][ell] = true;
-    if (p->gexec) {
+    if (p->gexec) {  // the captured step holds the old pointer
       (void)hipGraphExecDestroy(p->gexec);
       p->gexec = nullptr;
     }
@@ -857,6 +906,23 @@ extern "C" int expint_run(expint_plan* p, void* U, double t0, int nsteps, int us
     p->g_stream = s;
   }
   for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(p->gexec, s));
+  return EXPINT_OK;
+}
+
+extern "C" int expint_plan_check_finite(expint_plan* p, const void* U, void* stream) {
+  if (!p || !U) return set_error(EXPINT_EINVAL, "NULL plan or state");
+  if (!aligned16(U)) return set_error(EXPINT_EINVAL, "U must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long count = p->N * (p->dtype == EXPINT_C128 ? 2 : 1);
+  TRY(launch_finite_check(static_cast<const double*>(U), count, p->d_flag, s));
+  int flag = 0;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIP_TRY(hipMemset(p->d_flag, 0, sizeof(int)));
+    HIP_TRY(hipDeviceSynchronize());
+    return set_error(EXPINT_ENONFINITE, "the state holds inf or nan");
+  }
   return EXPINT_OK;
 }
 

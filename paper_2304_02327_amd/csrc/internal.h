@@ -159,5 +159,7 @@ int launch_lawson_stage(int dtype, long N, const void* U, void* Wa, void* Wb, do
 // clock = {t0, 0} / clock[1] += 1 (one thread; graph-capturable, no memset)
 int launch_clock_set(double* clock, double t0, void* stream);
 int launch_clock_tick(double* clock, void* stream);
+// flag[0] |= 1 if any of count doubles at x is not finite (flag: device int)
+int launch_finite_check(const double* x, long count, int* flag, void* stream);
 
 }  // namespace expint

@@ -66,11 +66,19 @@ void matmul(int n, const T* A, const T* B, T* C) {
   }
   std::vector<std::thread> pool;
   const int per = (n + (int)nt - 1) / (int)nt;
-  for (unsigned t = 0; t < nt; ++t) {
-    const int j0 = (int)t * per, j1 = j0 + per < n ? j0 + per : n;
-    if (j0 >= j1) break;
-    pool.emplace_back(cols, j0, j1);
+  int assigned = 0;  // columns [0, assigned) belong to started threads
+  try {
+    pool.reserve(nt);
+    for (unsigned t = 0; t < nt; ++t) {
+      const int j0 = (int)t * per, j1 = j0 + per < n ? j0 + per : n;
+      if (j0 >= j1) break;
+      pool.emplace_back(cols, j0, j1);
+      assigned = j1;
+    }
+  } catch (...) {
+    // no more threads: the calling thread computes the columns left over
   }
+  cols(assigned, n);
   for (auto& th : pool) th.join();
 }
 
@@ -154,7 +162,7 @@ int phi_setup_impl(int n, const T* A, int lda, double tau, int ell_max, T* out, 
   if (int rc = check_phi_args(n, A, lda, tau, ell_max, out, ldo); rc != EXPINT_OK) return rc;
   const size_t nn = (size_t)n * n;
   std::vector<T> X;
-  int s;
+  int s = 0;
   double norm1;
   if (int rc = scaled_input(n, A, lda, tau, 0.5, false, X, &s, &norm1); rc != EXPINT_OK)  // ||X / 2^s||_1 <= 1/2
     return rc;
@@ -314,7 +322,7 @@ int phi_setup_quad_impl(int n, const T* A, int lda, double tau, int ell_max, T* 
   if (int rc = check_phi_args(n, A, lda, tau, ell_max, out, ldo); rc != EXPINT_OK) return rc;
   const size_t nn = (size_t)n * n;
   std::vector<T> X;
-  int s;
+  int s = 0;
   double norm1;
   if (int rc = scaled_input(n, A, lda, tau, 1.0, true, X, &s, &norm1); rc != EXPINT_OK) return rc;
   const int L = ell_max;

@@ -345,4 +345,28 @@ int launch_clock_tick(double* clock, void* stream) {
   return check_launch("clock_tick");
 }
 
+// Non-finite check: sets flag[0] |= 1 if any of the `count` doubles is inf or
+// nan.  A wave that sees one issues a single atomic; no other write happens,
+// so the flag keeps what earlier checks left until the host clears it.
+namespace {
+__global__ __launch_bounds__(256) void k_finite_check(const double* __restrict__ x, long count, int* flag) {
+  bool bad = false;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const double v = x[i];
+    bad |= !(fabs(v) <= 1.7976931348623157e308);
+  }
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+}  // namespace
+
+int launch_finite_check(const double* x, long count, int* flag, void* stream) {
+  if (count <= 0) return EXPINT_OK;
+  long blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_finite_check, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), x,
+                     count, flag);
+  return check_launch("finite_check");
+}
+
 }  // namespace expint

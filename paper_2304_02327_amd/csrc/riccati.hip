@@ -68,11 +68,16 @@ struct PhiJob {
   int n;
 };
 
+// Device status words of a batched plan (cleared by expint_batch_status)
+constexpr int kStatusSquarings = 0;  // a phi_1 needed more than smax squarings
+constexpr int kStatusNonFinite = 1;  // a non-finite 1-norm or state
+
 // One workgroup of 16 waves per matrix: the 1-norm (largest absolute column
 // sum), the scaling, and the first Horner term.  Wave w takes columns w, w + 16,
 // ...; lanes run down a column (coalesced).
 constexpr int kPrepWaves = 16;
-__global__ __launch_bounds__(64 * kPrepWaves) void k_phi_prep(const PhiJob* __restrict__ jobs, int smax) {
+__global__ __launch_bounds__(64 * kPrepWaves) void k_phi_prep(const PhiJob* __restrict__ jobs, int smax,
+                                                               int* __restrict__ status) {
   const PhiJob jb = jobs[blockIdx.x];
   const int n = jb.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ double colmax[kPrepWaves];
@@ -94,14 +99,20 @@ __global__ __launch_bounds__(64 * kPrepWaves) void k_phi_prep(const PhiJob* __re
     int sc = 0;
     if (!(nu <= 1.7976931348623157e308)) {
       sc = smax;  // inf or nan: the result is not finite either way
+      atomicOr(status + kStatusNonFinite, 1);
     } else {
-      while (nu > 0.5 && sc < smax) {
+      // the count that brings ||Y||_1 to <= 1/2 (at most 1100 halvings of a
+      // finite norm); more than the plan's squaring phases is flagged and capped
+      while (nu > 0.5) {
         nu *= 0.5;
         ++sc;
       }
+      sc += sc & 1;  // even: the squarings end in the buffer they start from
+      if (sc > smax) {
+        atomicOr(status + kStatusSquarings, 1);
+        sc = smax;
+      }
     }
-    sc += sc & 1;  // even: the squarings end in the buffer they start from
-    if (sc > smax) sc = smax;
     s_sh = sc;
     *jb.s = sc;
   }
@@ -158,6 +169,7 @@ struct expint_batch_plan {
   void* ddesc = nullptr;
   long* dstart = nullptr;
   PhiJob* djobs = nullptr;
+  int* dstatus = nullptr;     // two status words (kStatus*)
   size_t desc_cap = 0, start_cap = 0;
   const void* d_U = nullptr;
   const void* d_ws = nullptr;
@@ -171,6 +183,7 @@ void free_batch(expint_batch_plan* p) {
   for (double* q : {p->dA1, p->dP1a, p->dP2a, p->dA2, p->dP1b, p->dP2b, p->dA2T})
     if (q) (void)hipFree(q);
   if (p->djobs) (void)hipFree(p->djobs);
+  if (p->dstatus) (void)hipFree(p->dstatus);
   if (p->ddesc) (void)hipFree(p->ddesc);
   if (p->dstart) (void)hipFree(p->dstart);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -439,7 +452,8 @@ int enqueue_batch_step(expint_batch_plan* p, hipStream_t s) {
     const int rc = launch_grouped_gemm(ph.bk, d, p->dstart + ph.start_off, ph.ndesc, ph.tiles, s);
     if (rc != EXPINT_OK) return rc;
     if ((int)k == p->prep_after) {
-      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(64 * kPrepWaves), 0, s, p->djobs, p->smax);
+      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(64 * kPrepWaves), 0, s, p->djobs, p->smax,
+                         p->dstatus);
       const hipError_t err = hipGetLastError();
       if (err != hipSuccess) return set_error(EXPINT_EHIP, "phi prep launch failed: %s", hipGetErrorString(err));
     }
@@ -458,11 +472,21 @@ int prepare(expint_batch_plan* p, double* U, void* ws) {
 
 }  // namespace
 
-extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count, const int* n1, const int* n2,
-                                             const double* const* A1, const double* const* A2, const double* B,
-                                             const double* C, double tau, int scheme) {
-  if (!out) return set_error(EXPINT_EINVAL, "plan output pointer is NULL");
-  *out = nullptr;
+namespace {
+
+// Frees a partly built plan when creation returns early or a host allocation throws.
+struct BatchPlanGuard {
+  expint_batch_plan* p = nullptr;
+  ~BatchPlanGuard() {
+    if (p) {
+      free_batch(p);
+      delete p;
+    }
+  }
+};
+
+int riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const int* n2, const double* const* A1,
+                        const double* const* A2, const double* B, const double* C, double tau, int scheme) {
   if (scheme != EXPINT_ETD2RK && scheme != EXPINT_ROSENBROCK_EULER)
     return set_error(EXPINT_ENOTSUP, "batched Riccati plans support ETD2RK and Rosenbrock-Euler (scheme %d)", scheme);
   const bool ros = scheme == EXPINT_ROSENBROCK_EULER;
@@ -477,7 +501,8 @@ extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count,
     total += (long)n1[i] * n2[i];
   }
   if (total * 8 >= (1L << 31)) return set_error(EXPINT_ENOTSUP, "batched state above 2 GiB");
-  expint_batch_plan* p = new (std::nothrow) expint_batch_plan();
+  BatchPlanGuard guard;
+  expint_batch_plan* p = guard.p = new (std::nothrow) expint_batch_plan();
   if (!p) return set_error(EXPINT_ENOMEM, "plan allocation failed");
   p->count = count;
   p->tau = tau;
@@ -511,7 +536,7 @@ extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count,
   std::vector<double> hA1(p->m1total), hP1a(p->m1total), hP2a(p->m1total);
   std::vector<double> hA2(p->m2total), hP1b(p->m2total), hP2b(p->m2total);
   std::vector<int> rcs(2 * count, EXPINT_OK);
-  auto work = [&](int job) {
+  auto work_job = [&](int job) {
     const int i = job / 2;
     const bool first = (job % 2) == 0;
     const int n = first ? n1[i] : n2[i];
@@ -527,20 +552,37 @@ extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count,
     std::memcpy(dst1, buf.data() + (size_t)n * n, sizeof(double) * n * n);
     std::memcpy(dst2, buf.data() + (size_t)2 * n * n, sizeof(double) * n * n);
   };
+  // a failure inside a job (host allocation) marks that job; no exception leaves a thread
+  auto work = [&](int job) noexcept {
+    try {
+      work_job(job);
+    } catch (...) {
+      rcs[job] = EXPINT_ENOMEM;
+    }
+  };
   {
     unsigned nt = std::thread::hardware_concurrency();
     nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
     std::vector<std::thread> pool;
     std::atomic<int> next{0};
-    for (unsigned t = 0; t < nt; ++t)
-      pool.emplace_back([&]() {
-        for (int job = next++; job < 2 * count; job = next++) work(job);
-      });
+    auto drain = [&]() noexcept {
+      for (int job = next++; job < 2 * count; job = next++) work(job);
+    };
+    try {
+      pool.reserve(nt);
+      for (unsigned t = 1; t < nt; ++t) pool.emplace_back(drain);
+    } catch (...) {
+      // fewer threads: the calling thread takes the remaining jobs below
+    }
+    drain();
+    phi_setup_single_threaded(false);  // the calling thread's later phi_setup calls may use threads again
     for (auto& th : pool) th.join();
   }
   int rc = EXPINT_OK;
-  for (int v : rcs)
-    if (v != EXPINT_OK) rc = v;
+  for (int job = 0; job < 2 * count && rc == EXPINT_OK; ++job)
+    if (rcs[job] != EXPINT_OK)
+      rc = set_error(rcs[job], "phi setup of instance %d (direction %d) failed (status %d)", job / 2, job % 2 + 1,
+                     rcs[job]);
   auto upload = [&](double** dst, const std::vector<double>& src) {
     if (rc != EXPINT_OK) return;
     if (hipMalloc(dst, src.size() * sizeof(double)) != hipSuccess) {
@@ -603,13 +645,32 @@ extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count,
   if (rc == EXPINT_OK && (hipMalloc(&p->ddesc, p->desc_cap) != hipSuccess ||
                           hipMalloc(reinterpret_cast<void**>(&p->dstart), p->start_cap * sizeof(long)) != hipSuccess))
     rc = set_error(EXPINT_ENOMEM, "device allocation for descriptors failed");
-  if (rc != EXPINT_OK) {
-    free_batch(p);
-    delete p;
-    return rc;
+  if (rc == EXPINT_OK) {
+    if (hipMalloc(reinterpret_cast<void**>(&p->dstatus), 2 * sizeof(int)) != hipSuccess)
+      rc = set_error(EXPINT_ENOMEM, "device allocation for the status words failed");
+    else if (hipMemset(p->dstatus, 0, 2 * sizeof(int)) != hipSuccess)
+      rc = set_error(EXPINT_EHIP, "status word initialisation failed");
   }
+  if (rc != EXPINT_OK) return rc;
+  guard.p = nullptr;
   *out = p;
   return EXPINT_OK;
+}
+
+}  // namespace
+
+extern "C" int expint_riccati_plan_create_ex(expint_batch_plan** out, int count, const int* n1, const int* n2,
+                                             const double* const* A1, const double* const* A2, const double* B,
+                                             const double* C, double tau, int scheme) {
+  if (!out) return set_error(EXPINT_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  try {
+    return riccati_plan_create(out, count, n1, n2, A1, A2, B, C, tau, scheme);
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "host allocation failed while creating the batched plan");
+  } catch (...) {
+    return set_error(EXPINT_ENOMEM, "host resources exhausted while creating the batched plan");
+  }
 }
 
 extern "C" int expint_riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const int* n2,
@@ -676,6 +737,29 @@ extern "C" int expint_batch_run(expint_batch_plan* p, double* U, int nsteps, int
   }
   for (int k = 0; k < nsteps; ++k)
     if (hipGraphLaunch(p->gexec, s) != hipSuccess) return set_error(EXPINT_EHIP, "graph launch failed");
+  return EXPINT_OK;
+}
+
+extern "C" int expint_batch_status(expint_batch_plan* p, const double* U, void* stream) {
+  if (!p) return set_error(EXPINT_EINVAL, "plan is NULL");
+  if (U && (reinterpret_cast<uintptr_t>(U) & 15u)) return set_error(EXPINT_EINVAL, "U must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (U) {
+    const int rc = launch_finite_check(U, p->total, p->dstatus + kStatusNonFinite, s);
+    if (rc != EXPINT_OK) return rc;
+  }
+  int st[2] = {0, 0};
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(st, p->dstatus, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return set_error(EXPINT_EHIP, "reading the batched plan's status failed");
+  if (st[0] || st[1]) {
+    if (hipMemset(p->dstatus, 0, sizeof(st)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      return set_error(EXPINT_EHIP, "clearing the batched plan's status failed");
+  }
+  if (st[kStatusSquarings])
+    return set_error(EXPINT_ENUMERIC, "a Jacobian direction needed more than the plan's %d squarings: its phi_1 is "
+                     "inaccurate", p->smax);
+  if (st[kStatusNonFinite]) return set_error(EXPINT_ENONFINITE, "the state or a Jacobian direction is not finite");
   return EXPINT_OK;
 }
 

@@ -245,3 +245,42 @@ def test_fused_modes12_query(monkeypatch):
     assert B.lib.tucker_fuses_modes12(2, n, 0, 9, ctypes.byref(out)) == B.EINVAL
     assert B.lib.tucker_fuses_modes12(2, n, 0, 0, None) == B.EINVAL
     assert out.value == 7
+
+
+def test_operand_limits_rejected_before_any_work():
+    """Tensors of 2 GiB or more (one mu-mode product operand) and exact-slice digit
+    planes past their limits are refused when the plan is made or tucker_apply is
+    called, with ENOTSUP, before anything touches the device."""
+    h = ctypes.c_void_p(None)
+    prob = B._Problem()
+    prob.d = 3
+    for mu in range(3):
+        prob.n[mu] = 650  # 650^3 doubles = 2.2 GB
+    prob.tau = 1e-3
+    prob.scheme = 3
+    prob.nonlin = 2
+    A = np.zeros((1, 1))
+    for mu in range(3):
+        prob.A[mu] = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # never read: the check comes first
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
+    assert "2 GiB" in B.lib.expint_last_error().decode()
+    assert h.value is None
+    prob.dtype = 1  # 512^3 complex128 = 2.1 GB
+    prob.nonlin = 3
+    for mu in range(3):
+        prob.n[mu] = 512
+    assert B.lib.expint_plan_create(ctypes.byref(h), ctypes.byref(prob)) == B.ENOTSUP
+    n = (ctypes.c_int * 3)(650, 650, 650)
+    ptrs = (ctypes.c_void_p * 3)(16, 16, 16)
+    assert B.lib.tucker_apply(3, n, ptrs, 16, 32, 1.0, 0.0, 0, 0, None, 0, None) == B.ENOTSUP
+    # exact slice: n_mu above 65535
+    n2 = (ctypes.c_int * 2)(70000, 2)
+    ptrs2 = (ctypes.c_void_p * 2)(16, 16)
+    assert B.lib.tucker_apply(2, n2, ptrs2, 16, 32, 1.0, 0.0, 0, B.PREC_SLICED, None, 0, None) == B.ENOTSUP
+    assert "65535" in B.lib.expint_last_error().decode()
+
+
+def test_status_entry_points_validate():
+    assert B.lib.expint_plan_check_finite(None, 16, None) == B.EINVAL
+    assert B.lib.expint_batch_status(None, None, None) == B.EINVAL
+    assert B.ENONFINITE == -6
