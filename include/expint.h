@@ -152,6 +152,26 @@ int tucker_apply(int d, const int* n, const void* const* M, const void* V, void*
                  double alpha, double beta, int dtype, int precision,
                  void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * tucker_apply_noalloc -- tucker_apply for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments and kernels as tucker_apply, without
+ * ws / ws_bytes.  The intermediates tucker_workspace_size() would count live in
+ * a fixed device array of EXPINT_NOALLOC_SCRATCH_BYTES bytes that the library
+ * keeps on each device it runs on until the process ends.  Nothing is
+ * allocated; the first call on a device looks up that device's array address.
+ * Every call on one device shares the array, so calls that overlap on one
+ * device (concurrent streams, or threads without ordering) race; calls
+ * ordered on one stream are safe.  The array needs no clearing: each call
+ * writes every scratch byte it reads.  Results equal tucker_apply's bitwise.
+ * Errors: as tucker_apply, and ENOTSUP when the shape needs more scratch than
+ * EXPINT_NOALLOC_SCRATCH_BYTES (e.g. FP64 tensors above 4 Mi elements with
+ * three or more modes), before anything is enqueued.
+ */
+#define EXPINT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tucker_apply_noalloc(int d, const int* n, const void* const* M, const void* V, void* W,
+                         double alpha, double beta, int dtype, int precision, void* stream);
+
 /* tucker_workspace_size -- bytes of workspace tucker_apply needs for this
  * shape, element type and precision (every M non-NULL; fewer modes need no
  * more).  Errors: EINVAL for a bad shape, dtype or precision. */

@@ -10,6 +10,7 @@ from ._binding import (  # noqa: F401
     EXPORTED_SYMBOLS,
     F64,
     LIB_PATH,
+    NOALLOC_SCRATCH_BYTES,
     NONLIN,
     PREC_BF16X3,
     PREC_FP32,
@@ -24,6 +25,7 @@ from ._binding import (  # noqa: F401
     tensor_from_device,
     tensor_to_device,
     tucker_apply,
+    tucker_apply_noalloc,
     tucker_workspace_size,
     tucker_fuses_modes12,
     version,

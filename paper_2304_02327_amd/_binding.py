@@ -28,6 +28,7 @@ PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_SLICED = 0, 1, 2, 3
 ROSENBROCK_EULER = 4  # batched Riccati plans only
 SCHEMES = {"lawson_euler": 0, "lawson2b": 1, "exp_euler": 2, "etd2rk": 3}
 NONLIN = {"none": 0, "allen_cahn": 1, "u2_1mu": 2, "cubic_nls": 3, "adr_paper": 4}
+NOALLOC_SCRATCH_BYTES = 64 << 20  # EXPINT_NOALLOC_SCRATCH_BYTES
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "slice": PREC_SLICED}
 
 
@@ -52,6 +53,8 @@ def _load():
     lib.phi_setup_ex.argtypes = [c_int, dp, c_int, c_double, c_int, c_int, c_int, dp, c_int]
     lib.tucker_apply.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p, c_void_p,
                                  c_double, c_double, c_int, c_int, c_void_p, c_size_t, c_void_p]
+    lib.tucker_apply_noalloc.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p,
+                                         c_void_p, c_double, c_double, c_int, c_int, c_void_p]
     lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_size_t)]
     lib.tucker_fuses_modes12.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_int)]
     lib.expint_plan_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_void_p]
@@ -84,7 +87,8 @@ def _load():
 lib = _load()
 
 EXPORTED_SYMBOLS = (
-    "phi_setup", "phi_setup_z", "phi_setup_ex", "tucker_apply", "tucker_workspace_size", "tucker_fuses_modes12",
+    "phi_setup", "phi_setup_z", "phi_setup_ex", "tucker_apply", "tucker_apply_noalloc", "tucker_workspace_size",
+    "tucker_fuses_modes12",
     "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_check_finite", "expint_plan_destroy",
     "expint_last_error",
@@ -226,12 +230,7 @@ def tucker_fuses_modes12(n: Sequence[int], dtype: int = F64, precision=PREC_FP64
     return bool(out.value)
 
 
-def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
-                 precision=PREC_FP64, ws=None, stream=None):
-    """W = alpha * (V x_1 M_1 ... x_d M_d) + beta * W on the device (M_mu = None: identity).
-    precision: a PREC_* code or one of "fp64", "fp32", "bf16x3", "slice"."""
-    precision = _precision_code(precision)
-    import torch
+def _tucker_args(Ms: Sequence, V, W):
     _check_device_tensor(V, "V")
     _check_device_tensor(W, "W")
     n = _sizes_of(V)
@@ -248,6 +247,16 @@ def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
             if tuple(M.shape) != (n[mu], n[mu]) or M.dtype != V.dtype:
                 raise ValueError(f"M[{mu}] must be {n[mu]}x{n[mu]} of {V.dtype}")
             ptrs[mu] = M.data_ptr()
+    return n, d, dt, ptrs
+
+
+def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
+                 precision=PREC_FP64, ws=None, stream=None):
+    """W = alpha * (V x_1 M_1 ... x_d M_d) + beta * W on the device (M_mu = None: identity).
+    precision: a PREC_* code or one of "fp64", "fp32", "bf16x3", "slice"."""
+    precision = _precision_code(precision)
+    import torch
+    n, d, dt, ptrs = _tucker_args(Ms, V, W)
     need = tucker_workspace_size(n, dt, precision)
     if ws is None and need > 0:
         ws = torch.empty(need, dtype=torch.uint8, device=V.device)
@@ -256,6 +265,19 @@ def tucker_apply(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
     arr = (ctypes.c_int * d)(*n)
     _check(lib.tucker_apply(d, arr, ptrs, V.data_ptr(), W.data_ptr(), float(alpha), float(beta), dt,
                             int(precision), ws_ptr, ws_bytes, _stream_handle(stream)))
+    return W
+
+
+def tucker_apply_noalloc(Ms: Sequence, V, W, alpha: float = 1.0, beta: float = 0.0,
+                         precision=PREC_FP64, stream=None):
+    """tucker_apply with its intermediates in the library's fixed device scratch array
+    (NOALLOC_SCRATCH_BYTES per device): no workspace argument and no allocation.
+    Calls that overlap on one device race."""
+    precision = _precision_code(precision)
+    n, d, dt, ptrs = _tucker_args(Ms, V, W)
+    arr = (ctypes.c_int * d)(*n)
+    _check(lib.tucker_apply_noalloc(d, arr, ptrs, V.data_ptr(), W.data_ptr(), float(alpha), float(beta), dt,
+                                    int(precision), _stream_handle(stream)))
     return W
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -291,16 +292,17 @@ extern "C" int tucker_fuses_modes12(int d, const int* n, int dtype, int precisio
   return EXPINT_OK;
 }
 
-extern "C" int tucker_apply(int d, const int* n, const void* const* M, const void* V, void* W,
-                            double alpha, double beta, int dtype, int precision, void* ws,
-                            size_t ws_bytes, void* stream) {
-  long N;
-  TRY(validate_shape(d, n, &N));
+// Validation shared by tucker_apply and tucker_apply_noalloc: every argument
+// except the workspace, then the workspace layout the call needs.
+static int tucker_validate(int d, const int* n, const void* const* M, const void* V, void* W, double alpha,
+                           double beta, int dtype, int precision, long* N, size_t* tens, size_t* digs,
+                           size_t* mdigs) {
+  TRY(validate_shape(d, n, N));
   if (dtype != EXPINT_F64 && dtype != EXPINT_C128) return set_error(EXPINT_EINVAL, "unknown dtype %d", dtype);
   if (!valid_precision(precision)) return set_error(EXPINT_EINVAL, "tucker_apply: unknown precision %d", precision);
   if ((precision == EXPINT_PREC_BF16X3 || precision == EXPINT_PREC_SLICED) && dtype != EXPINT_F64)
     return set_error(EXPINT_ENOTSUP, "tucker_apply: complex data supports FP64 or FP32 (complex64) contraction");
-  TRY(check_operand_limits(d, n, N, dtype, precision));
+  TRY(check_operand_limits(d, n, *N, dtype, precision));
   if (!M || !V || !W) return set_error(EXPINT_EINVAL, "tucker_apply: NULL M, V or W");
   if (V == W) return set_error(EXPINT_EINVAL, "tucker_apply: V must not alias W");
   if (!aligned16(V) || !aligned16(W)) return set_error(EXPINT_EINVAL, "tucker_apply: V and W must be 16-byte aligned");
@@ -309,13 +311,13 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
     if (M[mu] && !aligned16(M[mu])) return set_error(EXPINT_EINVAL, "tucker_apply: M[%d] not 16-byte aligned", mu);
   const int modes = count_modes(d, M);
   if (modes == 0) return set_error(EXPINT_EINVAL, "tucker_apply: every M[mu] is NULL (nothing to apply)");
-  size_t tens, digs, mdigs;
-  TRY(tucker_ws_layout(d, n, N, dtype, precision, modes, &tens, &digs, &mdigs));
-  const size_t need = tens + digs + mdigs;
-  if (ws_bytes < need || (need > 0 && !ws))
-    return set_error(EXPINT_EINVAL, "tucker_apply: workspace of %zu bytes needed, %zu given", need, ws_bytes);
-  if (need > 0 && !aligned16(ws)) return set_error(EXPINT_EINVAL, "tucker_apply: workspace not 16-byte aligned");
-  char* w = static_cast<char*>(ws);
+  return tucker_ws_layout(d, n, *N, dtype, precision, modes, tens, digs, mdigs);
+}
+
+// The kernel sequence of a validated Tucker operator, with its workspace at w.
+static int tucker_enqueue(int d, const int* n, const void* const* M, const void* V, void* W, double alpha,
+                          double beta, int dtype, int precision, long N, size_t tens, size_t digs, char* w,
+                          void* stream) {
   Epilogue last;
   last.op = EPI_AXPBY;
   last.alpha = alpha;
@@ -336,6 +338,72 @@ extern "C" int tucker_apply(int d, const int* n, const void* const* M, const voi
   void* t0 = tens ? w : nullptr;
   void* t1 = tens ? w + (size_t)N * elem_size(dtype) : nullptr;
   return tucker_chain(dtype, precision, d, n, M, V, t0, t1, last, stream);
+}
+
+extern "C" int tucker_apply(int d, const int* n, const void* const* M, const void* V, void* W,
+                            double alpha, double beta, int dtype, int precision, void* ws,
+                            size_t ws_bytes, void* stream) {
+  long N;
+  size_t tens, digs, mdigs;
+  TRY(tucker_validate(d, n, M, V, W, alpha, beta, dtype, precision, &N, &tens, &digs, &mdigs));
+  const size_t need = tens + digs + mdigs;
+  if (ws_bytes < need || (need > 0 && !ws))
+    return set_error(EXPINT_EINVAL, "tucker_apply: workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  if (need > 0 && !aligned16(ws)) return set_error(EXPINT_EINVAL, "tucker_apply: workspace not 16-byte aligned");
+  return tucker_enqueue(d, n, M, V, W, alpha, beta, dtype, precision, N, tens, digs, static_cast<char*>(ws),
+                        stream);
+}
+
+// ---------------------------------------------------------------------------
+// tucker_apply_noalloc: the same kernels with the workspace in a fixed device array
+// ---------------------------------------------------------------------------
+
+// The intermediates of tucker_apply_noalloc.  Each device holds its own copy
+// for the life of the process; host code never passes this name to a kernel
+// or a copy (on the host it is a stand-in, not a device address) but the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[EXPINT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return set_error(EXPINT_ENOTSUP, "tucker_apply_noalloc: device ordinal %d beyond %d", dev, kScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(EXPINT_EHIP, "tucker_apply_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return EXPINT_OK;
+}
+}  // namespace
+
+extern "C" int tucker_apply_noalloc(int d, const int* n, const void* const* M, const void* V, void* W,
+                                    double alpha, double beta, int dtype, int precision, void* stream) {
+  long N;
+  size_t tens, digs, mdigs;
+  TRY(tucker_validate(d, n, M, V, W, alpha, beta, dtype, precision, &N, &tens, &digs, &mdigs));
+  const size_t need = tens + digs + mdigs;
+  if (need > (size_t)EXPINT_NOALLOC_SCRATCH_BYTES)
+    return set_error(EXPINT_ENOTSUP,
+                     "tucker_apply_noalloc: this shape needs %zu bytes of scratch, the fixed limit is %zu bytes "
+                     "(use tucker_apply with a workspace)",
+                     need, (size_t)EXPINT_NOALLOC_SCRATCH_BYTES);
+  void* ptr = nullptr;
+  if (need > 0) TRY(scratch_address(&ptr));
+  return tucker_enqueue(d, n, M, V, W, alpha, beta, dtype, precision, N, tens, digs, static_cast<char*>(ptr),
+                        stream);
 }
 
 // ---------------------------------------------------------------------------
