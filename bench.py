@@ -35,7 +35,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 PEAK_BF16_TFLOPS = 2516.6  # MI355X dense BF16 MFMA
 PEAK_INT8_TOPS = 5000.0    # MI355X dense INT8 MFMA
-SLICE_PRODUCTS = 26        # digit products a_i b_j (i + j <= 6) per multiply-add of the exact-slice path
+SLICE_PRODUCTS = 19        # digit products a_i b_j (i + j <= 5) per multiply-add of the exact-slice path
 PEAK_HBM_GBS = 8000.0
 
 
@@ -285,7 +285,7 @@ def bench_riccati(args, scheme="etd2rk"):
 
 SWEEP_PRECISIONS = ("fp32", "bf16x3", "slice", "fp64")  # FP64 last: its timed region gives `value`
 PREC_DTYPE = {"fp64": "f64", "fp32": "f32 (state f64)", "bf16x3": "bf16x3/f32acc (state f64)",
-              "slice": "int8 digits x6/int32 acc (state f64)"}
+              "slice": "int8 digits x5/int32 acc (state f64)"}
 # the stated bound of each precision's error against the FP64 oracle (rel-inf, a few steps)
 PREC_BOUND = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "slice": 1e-10}
 

@@ -53,11 +53,11 @@ extern "C" {
 #define EXPINT_PREC_FP32    1   /* operands rounded to FP32, FP32 MFMA */
 #define EXPINT_PREC_BF16X3  2   /* x = hi + lo (bf16, RNE); hi*hi + hi*lo + lo*hi, FP32 accumulate */
 #define EXPINT_PREC_SLICED  3   /* exact-slice: every operand fibre (a row of M, a fibre of the
-                                   tensor along the contracted mode) as 6 balanced base-128 int8
-                                   digits under one power-of-two exponent; the 26 digit products
-                                   a_i b_j with i + j <= 6 summed exactly in int32 on int8 MFMA
+                                   tensor along the contracted mode) as 5 balanced base-254 int8
+                                   digits under one power-of-two exponent; the 19 digit products
+                                   a_i b_j with i + j <= 5 summed exactly in int32 on int8 MFMA
                                    and combined in FP64.  Error of one contraction at most
-                                   2^-41 (max|v| sum|m| + max|m| sum|v|) + n 2^-44.6 max|m| max|v|
+                                   2^-38.9 (max|v| sum|m| + max|m| sum|v|) + n 2^-44.3 max|m| max|v|
                                    over the contracted fibres; FP64 between modes */
 
 /* time-stepping schemes (paper section 2; tensor forms in section 3.2) */
@@ -141,7 +141,7 @@ int phi_setup_ex(int n, const double* A, int lda, double tau, int ell_max, int m
  *              EXPINT_PREC_BF16X3: operands split into two bf16 parts, FP32
  *              accumulation -- both keep FP32 intermediates between modes and
  *              return FP64; EXPINT_PREC_SLICED (real data only, n[mu] <=
- *              65535): exact-slice digits on int8 MFMA, FP64 intermediates
+ *              26624): exact-slice digits on int8 MFMA, FP64 intermediates
  *   ws         device workspace of at least tucker_workspace_size() bytes
  *              (may be NULL when that size is 0)
  *   stream     hipStream_t

@@ -236,7 +236,7 @@ static int validate_shape(int d, const int* n, long* N) {
 
 // Operand limits of the kernels, checked before anything is enqueued: every
 // mu-mode product addresses its operands with 32-bit buffer offsets (below
-// 2 GiB per tensor), and the exact-slice digits need n_mu <= 65535 and each
+// 2 GiB per tensor), and the exact-slice digits need n_mu <= 26624 and each
 // digit plane (fibres x padded length) below 2^31 bytes.
 static int check_operand_limits(int d, const int* n, long N, int dtype, int precision) {
   const size_t bytes = (size_t)N * elem_size(dtype);
@@ -245,7 +245,8 @@ static int check_operand_limits(int d, const int* n, long N, int dtype, int prec
                      bytes);
   if (precision == EXPINT_PREC_SLICED)
     for (int mu = 0; mu < d; ++mu) {
-      if (n[mu] > 65535) return set_error(EXPINT_ENOTSUP, "exact-slice precision: n[%d] = %d exceeds 65535", mu, n[mu]);
+      if (n[mu] > kSliceMaxK)
+        return set_error(EXPINT_ENOTSUP, "exact-slice precision: n[%d] = %d exceeds %d", mu, n[mu], kSliceMaxK);
       const size_t plane = (size_t)(N / n[mu]) * (size_t)slice_kpad(n[mu]);
       if (plane >= (1ull << 31))
         return set_error(EXPINT_ENOTSUP, "exact-slice precision: digit plane of mode %d exceeds 2 GiB", mu + 1);

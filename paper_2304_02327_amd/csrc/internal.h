@@ -107,10 +107,12 @@ bool small2d_fits(int d, const int* n);
 int launch_small2d(const SmallArgs& a, void* stream);
 
 // Exact-slice contraction (EXPINT_PREC_SLICED): each operand fibre is cut
-// into kSliceDigits balanced base-128 digits under one power-of-two exponent
+// into kSliceDigits balanced base-254 digits under one power-of-two exponent
 // and the digit products run exactly on int8 MFMA.  A digit buffer holds the
 // planes of `rows` fibres padded to slice_kpad(n) followed by their exponents.
-constexpr int kSliceDigits = 6;
+constexpr int kSliceDigits = 5;
+constexpr int kSliceProducts = 19;  // digit pairs (i, j) with i + j <= kSliceDigits
+constexpr int kSliceMaxK = 26624;  // longest contraction whose int32 level sums stay exact
 int slice_kpad(int n);
 size_t slice_digits_bytes(long rows, int n);
 // digits of the fibres along the middle index of V viewed as (s, n, r);

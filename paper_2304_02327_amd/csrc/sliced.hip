@@ -6,20 +6,22 @@
 //
 // Digits.  A fibre x[0..n) (the values a row of Aop or a column of Bop meets
 // along k) gets one power-of-two exponent E with max |x| < 2^(E-1), so
-// x' = x 2^-E lies in (-1/2, 1/2).  Six balanced base-128 digits follow by
-// repeated rounding: t = 128 x', a = rint(t), x' = t - a (exact in FP64), so
-//     x = 2^E sum_{i<6} a_i 128^-(i+1) + r,   a_i in [-64, 64],
-//     |r| <= 2^E 128^-6 / 2.
-// Digit products a_i b_j are at most 2^12 in magnitude; a level sum of at
-// most six of them over k stays exact in int32 for any K below 2^16.
+// x' = x 2^-E lies in (-1/2, 1/2).  Five balanced base-254 digits follow by
+// repeated rounding: t = 254 x', a = rint(t), x' = t - a, so
+//     x = 2^E (sum_{i<5} a_i 254^-(i+1) + r),   a_i in [-127, 127],
+//     |r| <= 254^-5 / 2 + 2^-46.
+// |t| <= 127 because |x'| <= 1/2, and t - rint(t) is exact in FP64; only the
+// product 254 x' rounds (2^-53 relative, the 2^-46 term above).  A digit
+// product is at most 127^2 < 2^14 in magnitude and a level holds at most five
+// of them per k, so a level sum over k stays exact in int32 for K <= 26624.
 //
-// Product.  sum_k x_k y_k = 2^(Ex+Ey) sum_L 128^-(L+2) acc_L with
-// acc_L = sum_{i+j=L} sum_k a_i,k b_j,k.  The 26 digit products with
-// i + j <= 6 run on int8 MFMA and accumulate exactly in int32; those with
-// i + j >= 7 (weight <= 128^-9 per k) are dropped, and the epilogue combines
-// the seven level sums in FP64.  With 2^E <= 4 max|x| the error of one
-// contraction is at most
-//     2^-41 (max|y| sum_k |x_k| + max|x| sum_k |y_k|) + K 2^-44.6 max|x| max|y|
+// Product.  sum_k x_k y_k = 2^(Ex+Ey) sum_L 254^-(L+2) acc_L with
+// acc_L = sum_{i+j=L} sum_k a_i,k b_j,k.  The 19 digit products with
+// i + j <= 5 run on int8 MFMA and accumulate exactly in int32; those with
+// i + j >= 6 (weight <= 254^-8 per k) are dropped, and the epilogue combines
+// the six level sums in FP64 by Horner's rule in powers of 1/254.  With
+// 2^E <= 4 max|x| the error of one contraction is at most
+//     2^-38.9 (max|y| sum_k |x_k| + max|x| sum_k |y_k|) + K 2^-44.3 max|x| max|y|
 // (digit truncation, then the dropped products), plus FP64 rounding.
 //
 // Layout.  Digit d of fibre R lives at dig + d * plane + R * Kpad + k, with k
@@ -32,6 +34,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
 
 #include "device_common.h"
 #include "internal.h"
@@ -42,6 +46,8 @@ namespace {
 
 constexpr int kDigits = kSliceDigits;
 constexpr int kLevels = kDigits + 1;  // level sums L = i + j = 0 .. kDigits
+constexpr double kBase = 254.0;
+constexpr double kInvBase = 1.0 / 254.0;
 constexpr int kNonFinite = 1 << 20;  // exponent marking a fibre with inf or nan
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -67,11 +73,11 @@ __device__ __forceinline__ double absmax(double mx, double x) {
   return (a > mx || a != a) ? a : mx;
 }
 
-// Six digits of x' = x 2^-E, one per byte lane `e` of word w[d].
+// The digits of x' = x 2^-E, one per byte lane `e` of word w[d].
 __device__ __forceinline__ void put_digits(double xs, unsigned (&w)[kDigits], int e) {
 #pragma unroll
   for (int d = 0; d < kDigits; ++d) {
-    const double t = xs * 128.0;
+    const double t = xs * kBase;
     const double a = __builtin_rint(t);
     xs = t - a;
     w[d] |= ((unsigned)(int)a & 0xffu) << (8 * e);
@@ -280,79 +286,126 @@ struct SliceGemmArgs {
 };
 
 // One TM x TQ output tile per workgroup of WGM x WGQ waves, each wave one
-// 32 x 32 block on v_mfma_i32_32x32x32_i8.  K runs in chunks of 64 staged
-// through LDS with a register prefetch of the next chunk.  LDS rows are the
-// 64 bytes of one chunk; 16-byte piece p of row r sits at p ^ ((r / 2) mod 4),
-// so the 8 lanes an LDS access serves per cycle hit disjoint banks both when
-// a thread stores its piece and when a fragment (8 rows, one piece) is read.
+// 32 x 32 block on v_mfma_i32_32x32x32_i8.  K runs in chunks of KC bytes per
+// row (32 or 64).  Each chunk travels from global memory straight into LDS
+// (buffer_load_dwordx4 ... lds: one instruction moves 1 KB, lane l writing
+// bytes 16 l .. 16 l + 15 of it), so no registers stage it, into one of S
+// stages: while the waves multiply chunk c, chunks c + 1 .. c + S - 2 are in
+// flight, and one barrier per chunk both publishes chunk c and frees the stage
+// of chunk c - 1 for chunk c + S - 1.  The loads are issued from inline
+// assembly, which has no register result (the data goes to LDS at the address
+// in M0), so the compiler neither tracks them nor waits for them: the kernel
+// counts them itself (vmcnt, in issue order) before each barrier.  In a stage, digit d holds the TM rows of
+// Aop and then the TQ rows of Bop, KC bytes each, in 16-byte pieces; piece p of
+// row r sits in slot p ^ swizzle(r) (the loading lane picks its piece
+// accordingly) with
+//     KC = 64: swizzle(r) = ((r / 2) ^ (r / 8)) mod 4,
+//     KC = 32: swizzle(r) = ((r / 4) ^ (r / 8)) mod 2,
+// so a fragment read (one piece of 32 consecutive rows) hits disjoint banks
+// within every 8 lanes (128 bytes) and within every 16 lanes (256 bytes),
+// whichever group the LDS serves per cycle.
 // v_mfma_i32_32x32x32_i8(X, Y) takes X[i][16 (l/32) + e] and Y[j][16 (l/32) + e]
 // (e < 16) in lane l and leaves sum_k X[i][k] Y[j][k] in lane j + 32 ((i/4) mod 2),
 // register 4 (i/8) + (i mod 4); with X = Bop and Y = Aop, 32 consecutive m
 // share 32 lanes.
-template <int TM, int TQ, int WGM, int WGQ>
-__global__ __launch_bounds__(64 * WGM * WGQ, 2) void k_sliced_gemm(SliceGemmArgs g) {
-  constexpr int NT = 64 * WGM * WGQ;
-  constexpr int D = kDigits;
-  constexpr int NL = kLevels;
-  constexpr int RS = 64;
-  static_assert(TM == 32 * WGM && TQ == 32 * WGQ, "one 32 x 32 block per wave");
-  constexpr int AP = TM * 4 / NT, BP = TQ * 4 / NT;  // 16-byte pieces per thread per digit
-  static_assert(AP * NT == TM * 4 && BP * NT == TQ * 4, "tile / thread mismatch");
-  __shared__ __attribute__((aligned(16))) int8_t As[D][TM * RS];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[D][TQ * RS];
+template <int WGM, int WGQ, int KC, int S>
+struct SliceTile {
+  static constexpr int NW = WGM * WGQ;
+  static constexpr int TM = 32 * WGM, TQ = 32 * WGQ;
+  static constexpr int PR = KC / 16;             // pieces per row
+  static constexpr int RPI = 64 / PR;            // rows per DMA instruction
+  static constexpr int ROWS = TM + TQ;           // rows of one digit in one stage
+  static constexpr int DBYTES = ROWS * KC;       // one digit of one stage
+  static constexpr int BBYTES = kDigits * DBYTES;
+  static constexpr int RG = ROWS / RPI;          // row groups per digit
+  static constexpr int NI = kDigits * RG;        // DMA instructions per chunk
+  static constexpr int NIW = (NI + NW - 1) / NW;  // per wave (the last one guarded)
+  static constexpr int NIW_MIN = NI / NW;         // issued by every wave
+  static_assert(KC == 32 || KC == 64, "chunk of 32 or 64 bytes");
+  static_assert(TM % RPI == 0 && TQ % RPI == 0, "row groups");
+  static_assert(S >= 2 && S <= 4, "2 to 4 stages");
+  static_assert((S - 2) * NIW_MIN <= 63, "vmcnt range");
+  __device__ static int swz(int r) {
+    return KC == 64 ? (((r >> 1) ^ (r >> 3)) & 3) : (((r >> 2) ^ (r >> 3)) & 1);
+  }
+};
+
+template <int BYTES>
+struct alignas(1024) StageMem {
+  int8_t b[BYTES];
+};
+
+// One LDS DMA load: 64 lanes x 16 bytes from the buffer `r` at voff + soff to
+// LDS bytes [lds, lds + 1024), lane l's at lds + 16 l.  Out-of-range offsets
+// read zeros.
+__device__ __forceinline__ void dma_b128(__amdgpu_buffer_rsrc_t r, unsigned lds, unsigned voff, int soff) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+               :
+               : "s"(lds), "v"(voff), "s"(r), "s"(soff)
+               : "memory");
+}
+
+template <typename P>
+__device__ __forceinline__ unsigned lds_offset(P* p) {
+  return (unsigned)(uintptr_t)(__attribute__((address_space(3))) P*)p;
+}
+
+template <int WGM, int WGQ, int KC, int S, int OCC>
+__global__ __launch_bounds__(64 * WGM * WGQ, OCC) void k_sliced_gemm(SliceGemmArgs g) {
+  using T = SliceTile<WGM, WGQ, KC, S>;
+  constexpr int NW = T::NW, TM = T::TM, TQ = T::TQ, NL = kLevels, PR = T::PR;
+  // one LDS object per stage, so that the compiler sees that reading one stage
+  // does not depend on the loads in flight into the others
+  __shared__ StageMem<T::BBYTES> st0;
+  __shared__ StageMem<T::BBYTES> st1;
+  __shared__ StageMem<S >= 3 ? T::BBYTES : 16> st2;
+  __shared__ StageMem<S >= 4 ? T::BBYTES : 16> st3;
+  auto stage = [&](int i) -> int8_t* {
+    return i == 0 ? st0.b : i == 1 ? st1.b : i == 2 ? st2.b : st3.b;
+  };
 
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   const long T_ = xcd_remap((long)blockIdx.x, nt);
   const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
   const long tm = tc.tm, tq = tc.tq, b = tc.b;
   const long m0 = tm * TM, q0 = tq * TQ;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm0 = (wave % WGM) * 32, wq0 = (wave / WGM) * 32;
 
-  // global -> register staging: piece p of a tile row covers k0 + 16 (p mod 4)
+  // DMA instruction u of this wave moves row group t mod RG of digit t / RG
+  // (t = wave + NW u); its lane l fills slot l mod PR of row RPI (t mod RG) + l / PR
   const unsigned abytes = (unsigned)g.a_plane, bbytes = (unsigned)g.b_plane;
-  unsigned avo[AP], bvo[BP];
+  unsigned voff[T::NIW];
 #pragma unroll
-  for (int p = 0; p < AP; ++p) {
-    const int piece = tid + p * NT, row = piece >> 2;
-    const long m = m0 + row;
-    avo[p] = m < g.M ? (unsigned)((m + b * g.a_rpb) * g.Kpad + 16 * (piece & 3)) : 0x80000000u;
+  for (int u = 0; u < T::NIW; ++u) {
+    const int t = wave + NW * u;
+    const int r = T::RPI * (t % T::RG) + lane / PR;
+    const int piece = (lane % PR) ^ T::swz(r);
+    unsigned o = 0x80000000u;
+    if (r < TM) {
+      const long m = m0 + r;
+      if (m < g.M) o = (unsigned)((m + b * g.a_rpb) * g.Kpad + 16 * piece);
+    } else {
+      const long q = q0 + (r - TM);
+      if (q < g.Q) o = (unsigned)((q + b * g.b_rpb) * g.Kpad + 16 * piece);
+    }
+    voff[u] = o;
   }
-#pragma unroll
-  for (int p = 0; p < BP; ++p) {
-    const int piece = tid + p * NT, row = piece >> 2;
-    const long q = q0 + row;
-    bvo[p] = q < g.Q ? (unsigned)((q + b * g.b_rpb) * g.Kpad + 16 * (piece & 3)) : 0x80000000u;
-  }
-  v4i ra[D][AP], rb[D][BP];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const __amdgpu_buffer_rsrc_t rsa = make_rsrc(g.A + d * g.a_plane, abytes);
-      const __amdgpu_buffer_rsrc_t rsb = make_rsrc(g.B + d * g.b_plane, bbytes);
-#pragma unroll
-      for (int p = 0; p < AP; ++p)
-        ra[d][p] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rsa, (int)avo[p], k0, 0));
-#pragma unroll
-      for (int p = 0; p < BP; ++p)
-        rb[d][p] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rsb, (int)bvo[p], k0, 0));
+  // DMA instruction u of chunk k0 into stage dst
+  auto issue_one = [&](int8_t* dst, int k0, int u) {
+    const int t = wave + NW * u;
+    if (u < T::NIW_MIN || t < T::NI) {
+      const int d = t / T::RG, rg = t % T::RG;
+      const bool isa = T::RPI * rg < TM;
+      const __amdgpu_buffer_rsrc_t rs =
+          isa ? make_rsrc(g.A + d * g.a_plane, abytes) : make_rsrc(g.B + d * g.b_plane, bbytes);
+      dma_b128(rs, lds_offset(dst + d * T::DBYTES + rg * 1024), voff[u], k0);
     }
   };
-  auto swz = [](int row, int pc) { return row * RS + 16 * (pc ^ ((row >> 1) & 3)); };
-  auto sstore = [&]() {
+  auto issue = [&](int8_t* dst, int k0) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-#pragma unroll
-      for (int p = 0; p < AP; ++p) {
-        const int piece = tid + p * NT;
-        *reinterpret_cast<v4i*>(&As[d][swz(piece >> 2, piece & 3)]) = ra[d][p];
-      }
-#pragma unroll
-      for (int p = 0; p < BP; ++p) {
-        const int piece = tid + p * NT;
-        *reinterpret_cast<v4i*>(&Bs[d][swz(piece >> 2, piece & 3)]) = rb[d][p];
-      }
-    }
+    for (int u = 0; u < T::NIW; ++u) issue_one(dst, k0, u);
   };
 
   v16i acc[NL];
@@ -361,27 +414,75 @@ __global__ __launch_bounds__(64 * WGM * WGQ, 2) void k_sliced_gemm(SliceGemmArgs
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[L][e] = 0;
 
+  // fragment byte offsets (k step ks of a chunk): A row wm0 + (lane mod 32),
+  // B row TM + wq0 + (lane mod 32), piece 2 ks + lane / 32
   const int fr = lane & 31, fh = lane >> 5;
-  const int nk = g.Kpad / 64;
-  gload(0);
-  for (int c = 0; c < nk; ++c) {
-    __syncthreads();
-    sstore();
-    __syncthreads();
-    if (c + 1 < nk) gload((c + 1) * 64);
+  auto frag = [](int row, int pc) { return row * KC + 16 * (pc ^ T::swz(row)); };
+  int ao[KC / 32], bo[KC / 32];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      v4i af[D], bf[D];
+  for (int ks = 0; ks < KC / 32; ++ks) {
+    ao[ks] = frag(wm0 + fr, 2 * ks + fh);
+    bo[ks] = frag(TM + wq0 + fr, 2 * ks + fh);
+  }
+  // Multiply the chunk in stage src; when `next` is set, the DMA instructions
+  // of the chunk at k0 into stage `next` are spread evenly between the MFMAs
+  // (pinned there by scheduling barriers), so that a burst of them does not
+  // hold up the MFMAs behind it while the memory pipeline's queue is full.
+  constexpr int NMF = (KC / 32) * kSliceProducts;  // MFMAs per chunk
+  constexpr int STEP = NMF / T::NIW > 0 ? NMF / T::NIW : 1;
+  auto compute = [&](const int8_t* src, int8_t* next, int k0) {
+    int t = 0;
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        af[i] = *reinterpret_cast<const v4i*>(&As[i][swz(wm0 + fr, 2 * ks + fh)]);
-        bf[i] = *reinterpret_cast<const v4i*>(&Bs[i][swz(wq0 + fr, 2 * ks + fh)]);
+    for (int ks = 0; ks < KC / 32; ++ks) {
+      v4i af[kDigits], bf[kDigits];
+#pragma unroll
+      for (int i = 0; i < kDigits; ++i) {
+        af[i] = *reinterpret_cast<const v4i*>(src + i * T::DBYTES + ao[ks]);
+        bf[i] = *reinterpret_cast<const v4i*>(src + i * T::DBYTES + bo[ks]);
       }
 #pragma unroll
-      for (int i = 0; i < D; ++i)
+      for (int i = 0; i < kDigits; ++i)
 #pragma unroll
-        for (int j = 0; j < D && i + j < NL; ++j)
+        for (int j = 0; j < kDigits && i + j < NL; ++j) {
           acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[j], af[i], acc[i + j], 0, 0, 0);
+          ++t;
+          if (t % STEP == 0 && t / STEP <= T::NIW && next) {
+            __builtin_amdgcn_sched_barrier(0);
+            issue_one(next, k0, t / STEP - 1);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+    }
+#pragma unroll
+    for (int u = NMF / STEP; u < T::NIW; ++u)
+      if (next) issue_one(next, k0, u);
+  };
+  // chunk c has landed in this wave once at most the loads of the S - 2 chunks
+  // issued after it are outstanding (loads complete in order); the barrier then
+  // covers every wave
+  auto landed = [&]() {
+    constexpr int n = (S - 2) * T::NIW_MIN;
+    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(n) : "memory");
+    __syncthreads();
+  };
+
+  const int nk = g.Kpad / KC;
+#pragma unroll
+  for (int c = 0; c < S - 1; ++c)
+    if (c < nk) issue(stage(c), c * KC);
+  for (int c0 = 0; c0 < nk; c0 += S) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      const int c = c0 + u;
+      if (c < nk) {
+        if (c + S - 2 >= nk) {
+          asm volatile("s_waitcnt vmcnt(0)" : : : "memory");  // the tail: fewer chunks after c
+          __syncthreads();
+        } else {
+          landed();
+        }
+        compute(stage(u), c + S - 1 < nk ? stage((u + S - 1) % S) : nullptr, (c + S - 1) * KC);
+      }
     }
   }
 
@@ -398,26 +499,58 @@ __global__ __launch_bounds__(64 * WGM * WGQ, 2) void k_sliced_gemm(SliceGemmArgs
       const int Eb = g.eb[q + b * g.b_rpb];
       double y = (double)acc[NL - 1][r];
 #pragma unroll
-      for (int L = NL - 2; L >= 0; --L) y = fma(y, 0.0078125, (double)acc[L][r]);
-      y = ldexp(y, Ea + Eb - 14);
+      for (int L = NL - 2; L >= 0; --L) y = fma(y, kInvBase, (double)acc[L][r]);
+      y = ldexp(y * (kInvBase * kInvBase), Ea + Eb);
       if (Ea >= kNonFinite || Eb >= kNonFinite) y = __builtin_nan("");
       f(cbase + m + g.ldc * q, y);
     }
   });
 }
 
-int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
-  constexpr int TM = 64, TQ = 64;  // 2 x 2 waves of 32 x 32
+// Tile shapes of the sliced product: TMxTQ outputs, w = waves, k = chunk bytes,
+// s = stages, o = workgroups per CU.  EXPINT_SLICE_TILE names one to force it.
+// Measured at 384^3 (MI355X): 64x64 on 4 waves, two workgroups per CU, is the
+// fastest of these (about 550 us per mode product, 30% of the int8 MFMA peak);
+// deeper pipelines (3-4 stages of 32-byte chunks) measured slower, since the
+// time goes to the volume the memory pipeline moves rather than to its latency.
+const char* const kSliceTileNames[] = {"64x64w4k64s2o2", "128x64w8k64s2o1", "64x128w8k64s2o1",
+                                       "64x64w4k32s2o3", "64x64w4k32s4o2",  "128x64w8k32s4o1"};
+constexpr int kNumSliceTiles = sizeof(kSliceTileNames) / sizeof(kSliceTileNames[0]);
+
+int slice_tile_override() {
+  const char* e = std::getenv("EXPINT_SLICE_TILE");
+  if (!e) return -1;
+  for (int i = 0; i < kNumSliceTiles; ++i)
+    if (std::strcmp(e, kSliceTileNames[i]) == 0) return i;
+  return -1;
+}
+
+template <int WGM, int WGQ, int KC, int S, int OCC>
+int launch_gemm_tile(SliceGemmArgs& g, hipStream_t st) {
+  constexpr int TM = 32 * WGM, TQ = 32 * WGQ;
   g.tiles_m = (g.M + TM - 1) / TM;
   g.tiles_q = (g.Q + TQ - 1) / TQ;
   g.m_fastest = g.Q > g.M * (g.a_rpb ? g.batches : 1);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "sliced product: too many tiles (%ld)", nt);
-  hipLaunchKernelGGL((k_sliced_gemm<TM, TQ, 2, 2>), dim3((unsigned)nt), dim3(256), 0, st, g);
+  hipLaunchKernelGGL((k_sliced_gemm<WGM, WGQ, KC, S, OCC>), dim3((unsigned)nt), dim3(64 * WGM * WGQ), 0, st, g);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "sliced product launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
+}
+
+int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
+  int choice = slice_tile_override();
+  if (choice < 0) choice = 0;
+  switch (choice) {
+    case 1: return launch_gemm_tile<4, 2, 64, 2, 1>(g, st);
+    case 2: return launch_gemm_tile<2, 4, 64, 2, 1>(g, st);
+    case 3: return launch_gemm_tile<2, 2, 32, 2, 3>(g, st);
+    case 4: return launch_gemm_tile<2, 2, 32, 4, 2>(g, st);
+    case 5: return launch_gemm_tile<4, 2, 32, 4, 1>(g, st);
+    default: return launch_gemm_tile<2, 2, 64, 2, 2>(g, st);
+  }
 }
 
 }  // namespace
@@ -434,7 +567,7 @@ int launch_slice(const double* V, long s, int n, long r, bool contiguous, void* 
   const long rows = s * r;
   const long plane = rows * (long)Kpad;
   if ((size_t)plane >= (1ull << 31)) return set_error(EXPINT_EINVAL, "sliced product: digit plane too large");
-  if (n > 65535) return set_error(EXPINT_EINVAL, "sliced product: n = %d exceeds 65535", n);
+  if (n > kSliceMaxK) return set_error(EXPINT_EINVAL, "sliced product: n = %d exceeds %d", n, kSliceMaxK);
   int8_t* dig = static_cast<int8_t*>(out);
   int* expo = reinterpret_cast<int*>(dig + ((size_t)kDigits * plane + 255) / 256 * 256);
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -273,11 +273,11 @@ def test_operand_limits_rejected_before_any_work():
     n = (ctypes.c_int * 3)(650, 650, 650)
     ptrs = (ctypes.c_void_p * 3)(16, 16, 16)
     assert B.lib.tucker_apply(3, n, ptrs, 16, 32, 1.0, 0.0, 0, 0, None, 0, None) == B.ENOTSUP
-    # exact slice: n_mu above 65535
-    n2 = (ctypes.c_int * 2)(70000, 2)
+    # exact slice: n_mu above 26624
+    n2 = (ctypes.c_int * 2)(30000, 2)
     ptrs2 = (ctypes.c_void_p * 2)(16, 16)
     assert B.lib.tucker_apply(2, n2, ptrs2, 16, 32, 1.0, 0.0, 0, B.PREC_SLICED, None, 0, None) == B.ENOTSUP
-    assert "65535" in B.lib.expint_last_error().decode()
+    assert "26624" in B.lib.expint_last_error().decode()
 
 
 def test_status_entry_points_validate():

@@ -1,10 +1,10 @@
 """Exact-slice contraction (EXPINT_PREC_SLICED) against the FP64 oracle.
 
-Every operand fibre is cut into six balanced base-128 int8 digits under a
+Every operand fibre is cut into five balanced base-254 int8 digits under a
 power-of-two exponent 2^E <= 4 max|x|, and the digit products a_i b_j with
-i + j <= 6 are summed exactly on int8 MFMA.  For one contraction
+i + j <= 5 are summed exactly on int8 MFMA.  For one contraction
 y = sum_k a_k b_k the library states the bound
-    |y_hat - y| <= 2^-41 (max|b| sum|a| + max|a| sum|b|) + K 2^-44.6 max|a| max|b|
+    |y_hat - y| <= 2^-38.9 (max|b| sum|a| + max|a| sum|b|) + K 2^-44.3 max|a| max|b|
 plus FP64 rounding of the combination; the single-mode tests check it element
 by element against the oracle's mu-mode product (a wrong digit weight, level
 or exponent breaks it by many orders of magnitude).  Tucker chains and whole
@@ -43,7 +43,7 @@ def _bound(V, M, mu):
     maxa = maxa.reshape(shape)
     suma = suma.reshape(shape)
     dot = mode_product(aV, aM, mu + 1)     # sum_k |a_k| |b_k|
-    return (2.0 ** -41 * (maxb * suma + maxa * sumb) + K * 2.0 ** -44.6 * maxa * maxb
+    return (2.0 ** -38.9 * (maxb * suma + maxa * sumb) + K * 2.0 ** -44.3 * maxa * maxb
             + 8 * np.finfo(float).eps * dot)
 
 
@@ -70,7 +70,7 @@ def test_single_mode_within_stated_bound(n, mu):
     assert ratio <= 1.0, ratio
     # and the error is far below what FP32 or BF16 operands would give
     err = rel_inf(got, ref)
-    assert err < 1e-11, err
+    assert err < 1e-10, err
 
 
 @pytest.mark.parametrize("n", [(7,), (33, 65), (40, 41, 42), (128, 128, 128), (17, 1, 70), (3, 4, 5, 6)])
@@ -99,7 +99,7 @@ def test_phi_matrices_of_the_workloads():
     Ms = [px.phi_setup(a, p.tau, 1)[1] for a in p.A]
     V = p.u0
     got = _sliced_tucker(Ms, V)
-    # stated bound with sum|phi row| ~ 1: a few 2^-41 per mode
+    # stated bound with sum|phi row| ~ 1: a few 2^-38.9 per mode
     err = rel_inf(got, tucker(V, Ms))
     assert err <= 1e-11, err
 
@@ -181,6 +181,26 @@ def test_set_phi_reslices():
     torch.cuda.synchronize()
     got = px.tensor_from_device(U)
     plan.close()
-    # digits of U carry ~2^-43 relative truncation; the original e^{tau A} would be off by O(tau)
+    # digits of U carry <= 2^-38.9 relative truncation per mode; the original e^{tau A} would be off by O(tau)
     err = rel_inf(got, p.u0 * 0.125)
-    assert err <= 1e-12, err
+    assert err <= 1e-11, err
+
+
+SLICE_TILES = ["64x64w4k64s2o2", "128x64w8k64s2o1", "64x128w8k64s2o1", "64x64w4k32s2o3", "64x64w4k32s4o2",
+               "128x64w8k32s4o1"]
+
+
+@pytest.mark.parametrize("tile", SLICE_TILES)
+def test_every_tile_shape(tile, monkeypatch):
+    """Each tile shape of the int8 product (forced through EXPINT_SLICE_TILE) on ragged
+    sizes: K of one, two and several chunks with a tail, rows and columns past the tile."""
+    monkeypatch.setenv("EXPINT_SLICE_TILE", tile)
+    rng = np.random.default_rng(21)
+    for n, mu in (((37, 70, 133), 0), ((37, 70, 133), 1), ((37, 70, 133), 2), ((200, 3, 5), 0)):
+        V = rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 3, size=n)
+        M = rng.standard_normal((n[mu], n[mu]))
+        Ms = [M if i == mu else None for i in range(len(n))]
+        got = _sliced_tucker(Ms, V)
+        ref = mode_product(V, M, mu + 1)
+        ratio = float((np.abs(got - ref) / _bound(V, M, mu)).max())
+        assert ratio <= 1.0, (tile, n, mu, ratio)
