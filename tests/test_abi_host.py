@@ -128,7 +128,7 @@ def test_sliced_workspace_layout():
 
     def digits(rows, k):
         kp = (k + 63) // 64 * 64
-        return _r256(6 * rows * kp) + _r256(4 * rows)
+        return _r256(5 * rows * kp) + _r256(4 * rows)  # five int8 digit planes, then the exponents
 
     expect = _r256(8 * N) + max(digits(N // k, k) for k in n) + sum(digits(k, k) for k in n)
     assert px.tucker_workspace_size(n, px.F64, px.PREC_SLICED) == expect
