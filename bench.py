@@ -358,6 +358,7 @@ def bench_sweep(args):
         finals[prec] = final
         leg = {"ms_per_step": ms / args.steps, "value": p.N * args.steps / (ms / 1e3), "unit": "DOF-steps/s",
                "dtype": PREC_DTYPE[prec], "wall_s_timed_region": wall, "plan_setup_s": round(setup_s, 3),
+               "launch_configuration": plan.describe().strip().splitlines(),
                "stated_bound_rel_inf": PREC_BOUND[prec],
                "roofline": tucker_roofline(args, p, px, dev, stream, U0, prec, "dr384")}
         if reps:
@@ -397,6 +398,7 @@ def bench_sweep(args):
         "tucker_tflops_whole_step": round(tucker_flops_per_step(p) * args.steps / (fp["ms_per_step"] * args.steps
                                                                                    / 1e3) / 1e12, 3),
         "roofline": fp["roofline"],
+        "launch_configuration": fp["launch_configuration"],
         "precision_legs": reduced,
     }
     if not args.no_cpu_baseline:
@@ -486,6 +488,7 @@ def bench_single(args):
         "config": {"workload": desc, "n": list(p.n), "scheme": p.scheme, "tau": p.tau,
                    "precision": args.precision, "graph": True},
         "wall_s_timed_region": wall,
+        "launch_configuration": plan.describe().strip().splitlines(),
         "repeat_ms_per_step": [round(x, 5) for x in repeats],
         "median_ms_per_step_of_repeats": round(sorted(repeats)[len(repeats) // 2], 5),
         "repeats_bitwise_equal_to_timed_state": bitwise,

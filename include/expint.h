@@ -172,6 +172,24 @@ int tucker_apply(int d, const int* n, const void* const* M, const void* V, void*
 int tucker_apply_noalloc(int d, const int* n, const void* const* M, const void* V, void* W,
                          double alpha, double beta, int dtype, int precision, void* stream);
 
+/*
+ * tucker_tune -- the autotuner: times every candidate launch configuration
+ * (tile shape, waves, pipeline depth, modes 1 and 2 in one launch or two) of
+ * every launch a tucker_apply of this shape, element type and precision (all
+ * modes present) makes, on scratch operands of the same sizes (hashed values), and
+ * keeps the fastest per launch shape and device architecture for the rest of
+ * the process.  Later tucker_apply / expint_step launches of those shapes use
+ * it; a shape tuned before is not timed again.  With the environment variable
+ * EXPINT_TUNE_CACHE naming a file, choices are read from it first and new ones
+ * appended, so a later process makes the same choices.  The candidates of a
+ * launch compute the same sums in the same order, so results do not depend on
+ * the choice.  Environment overrides (EXPINT_TILE, EXPINT_SLICE_TILE,
+ * EXPINT_M12) still take precedence.  Synchronous; allocates and frees its
+ * scratch (about three tensors).  FP32 and bf16x3 have one configuration each
+ * (nothing to tune).  Errors: EINVAL, ENOTSUP (as tucker_apply), ENOMEM, EHIP.
+ */
+int tucker_tune(int d, const int* n, int dtype, int precision, void* stream);
+
 /* tucker_workspace_size -- bytes of workspace tucker_apply needs for this
  * shape, element type and precision (every M non-NULL; fewer modes need no
  * more).  Errors: EINVAL for a bad shape, dtype or precision. */
@@ -209,6 +227,11 @@ typedef struct expint_problem {
                             digits of every phi in the plan */
   int phi_method;        /* construction of the phi matrices: EXPINT_PHI_TAYLOR (0) or
                             EXPINT_PHI_QUAD */
+  int tune;              /* 1: autotune the launch configuration of every mu-mode
+                            product (and of modes 1 and 2 together) the plan's
+                            steps make, at plan creation, as tucker_tune does;
+                            0: the library's measured defaults, or earlier tuning
+                            results for the same shapes */
 } expint_problem;
 
 /*
@@ -254,6 +277,13 @@ int expint_step(expint_plan* plan, void* U, double t, void* ws, void* stream);
  */
 int expint_run(expint_plan* plan, void* U, double t0, int nsteps, int use_graph,
                void* ws, void* stream);
+
+/* expint_plan_describe -- the launch configuration each mu-mode product (and
+ * the launch of modes 1 and 2) of the plan's steps uses, one line per launch
+ * shape: "family sizes: candidate (tuned, us)" or ": default".  Writes at most
+ * len bytes including the terminating NUL into buf; *needed (optional) gets the
+ * full length + 1.  Errors: EINVAL. */
+int expint_plan_describe(const expint_plan* plan, char* buf, size_t len, size_t* needed);
 
 /* expint_plan_is_fused -- *fused = 1 if the plan runs its steps in the fused
  * small-problem launch described at expint_run, else 0.  Errors: EINVAL. */

@@ -28,5 +28,6 @@ from ._binding import (  # noqa: F401
     tucker_apply_noalloc,
     tucker_workspace_size,
     tucker_fuses_modes12,
+    tucker_tune,
     version,
 )

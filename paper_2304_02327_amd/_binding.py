@@ -56,6 +56,8 @@ def _load():
     lib.tucker_apply_noalloc.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_void_p), c_void_p,
                                          c_void_p, c_double, c_double, c_int, c_int, c_void_p]
     lib.tucker_workspace_size.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_size_t)]
+    lib.tucker_tune.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, c_void_p]
+    lib.expint_plan_describe.argtypes = [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]
     lib.tucker_fuses_modes12.argtypes = [c_int, ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_int)]
     lib.expint_plan_create.argtypes = [ctypes.POINTER(c_void_p), ctypes.c_void_p]
     lib.expint_plan_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
@@ -88,8 +90,8 @@ lib = _load()
 
 EXPORTED_SYMBOLS = (
     "phi_setup", "phi_setup_z", "phi_setup_ex", "tucker_apply", "tucker_apply_noalloc", "tucker_workspace_size",
-    "tucker_fuses_modes12",
-    "expint_plan_create", "expint_plan_workspace_size", "expint_plan_set_phi",
+    "tucker_fuses_modes12", "tucker_tune",
+    "expint_plan_create", "expint_plan_describe", "expint_plan_workspace_size", "expint_plan_set_phi",
     "expint_step", "expint_run", "expint_plan_is_fused", "expint_plan_check_finite", "expint_plan_destroy",
     "expint_last_error",
     "expint_version",
@@ -112,6 +114,7 @@ class _Problem(ctypes.Structure):
         ("dtype", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("phi_method", ctypes.c_int),
+        ("tune", ctypes.c_int),
     ]
 
 
@@ -220,6 +223,13 @@ def tucker_workspace_size(n: Sequence[int], dtype: int = F64, precision=PREC_FP6
     return out.value
 
 
+def tucker_tune(n: Sequence[int], dtype: int = F64, precision=PREC_FP64, stream=None):
+    """Autotune the launch configurations of a tucker_apply of these sizes (synchronous)."""
+    d = len(n)
+    arr = (ctypes.c_int * d)(*n)
+    _check(lib.tucker_tune(d, arr, dtype, _precision_code(precision), _stream_handle(stream)))
+
+
 def tucker_fuses_modes12(n: Sequence[int], dtype: int = F64, precision=PREC_FP64) -> bool:
     """True if a Tucker operator of these sizes (M_1 and M_2 present) runs modes 1
     and 2 as one launch."""
@@ -293,7 +303,7 @@ class Plan:
 
     def __init__(self, A: Sequence[np.ndarray], tau: float, scheme: str, nonlin: str,
                  g_param: float = 0.0, precision: str = "fp64", device="cuda", g_param2: float = 0.0,
-                 phi_method: str = "taylor"):
+                 phi_method: str = "taylor", tune: bool = True):
         import torch
         A = [np.asarray(a) for a in A]
         cplx = any(np.iscomplexobj(a) for a in A) or nonlin == "cubic_nls"
@@ -319,6 +329,7 @@ class Plan:
         prob.dtype = self.dtype
         prob.precision = PRECISIONS[precision]
         prob.phi_method = PHI_METHODS[phi_method]
+        prob.tune = 1 if tune else 0
         self._handle = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
             _check(lib.expint_plan_create(ctypes.byref(self._handle), ctypes.byref(prob)))
@@ -326,6 +337,14 @@ class Plan:
         _check(lib.expint_plan_workspace_size(self._handle, ctypes.byref(size)))
         self.workspace_bytes = size.value
         self.ws = torch.empty(max(self.workspace_bytes, 16), dtype=torch.uint8, device=self.device)
+
+    def describe(self) -> str:
+        """The launch configuration of each mu-mode product of the plan's steps (tuned or default)."""
+        need = ctypes.c_size_t(0)
+        _check(lib.expint_plan_describe(self._handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.expint_plan_describe(self._handle, buf, need.value, None))
+        return buf.value.decode()
 
     @property
     def fused(self) -> bool:

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libexpint.so")
 
-HIP_SOURCES = ["api.hip", "mode_product.hip", "pointwise.hip", "riccati.hip", "sliced.hip", "small.hip", "modes12.hip"]
+HIP_SOURCES = ["api.hip", "mode_product.hip", "pointwise.hip", "riccati.hip", "sliced.hip", "small.hip", "modes12.hip",
+               "tune.hip"]
 CXX_SOURCES = ["phi_setup.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -57,11 +58,16 @@ void mode_view(int d, const int* n, int mu, long* s, long* r) {
 }
 
 // Modes 1 and 2 run as one launch (FP64 real data, n2 <= 128) unless
-// EXPINT_FUSE12=0, or EXPINT_TILE forces a single-mode tile on every mode.
+// EXPINT_FUSE12=0, EXPINT_TILE forces a single-mode tile on every mode, or the
+// autotuner (or EXPINT_M12=off) found the two single-mode launches faster.
 bool fuse12_allowed(int dtype, int precision, int d, const int* n) {
   const char* fenv = std::getenv("EXPINT_FUSE12");
-  return precision == EXPINT_PREC_FP64 && dtype == EXPINT_F64 && d >= 2 && modes12_fits(n[0], n[1]) &&
-         !(fenv && fenv[0] == '0') && !std::getenv("EXPINT_TILE");
+  if (!(precision == EXPINT_PREC_FP64 && dtype == EXPINT_F64 && d >= 2 && modes12_fits(n[0], n[1]) &&
+        !(fenv && fenv[0] == '0') && !std::getenv("EXPINT_TILE")))
+    return false;
+  long r = 1;
+  for (int k = 2; k < d; ++k) r *= n[k];
+  return tune_choice(modes12_key(n[0], n[1], r)) != modes12_shape_count();
 }
 
 // Tucker chain V x_1 M_1 ... x_d M_d with ping-pong buffers; the last applied
@@ -852,7 +858,46 @@ extern "C" int expint_plan_create(expint_plan** out, const expint_problem* prob)
     p->small = allowed && small2d_fits(p->d, p->n) && p->dtype == EXPINT_F64 &&
                p->precision == EXPINT_PREC_FP64 && !p->timedep;
   }
+  if (prob->tune && !p->small) {
+    const int trc = tune_tucker_shapes(p->d, p->n, p->dtype, p->precision, nullptr);
+    if (trc != EXPINT_OK) {
+      free_plan_memory(p);
+      delete p;
+      return trc;
+    }
+  }
   *out = p;
+  return EXPINT_OK;
+}
+
+extern "C" int expint_plan_describe(const expint_plan* p, char* buf, size_t len, size_t* needed) {
+  if (!p || (!buf && len > 0)) return set_error(EXPINT_EINVAL, "NULL plan or buffer");
+  std::string s;
+  if (p->small) {
+    s = "k_small2d: whole run in one workgroup\n";
+  } else if (p->precision == EXPINT_PREC_FP64 || p->precision == EXPINT_PREC_SLICED) {
+    const bool f12 = fuse12_allowed(p->dtype, p->precision, p->d, p->n);
+    if (p->precision == EXPINT_PREC_FP64 && p->dtype == EXPINT_F64 && p->d >= 2 && modes12_fits(p->n[0], p->n[1])) {
+      long r = 1;
+      for (int k = 2; k < p->d; ++k) r *= p->n[k];
+      s += tune_describe(modes12_key(p->n[0], p->n[1], r)) + (f12 ? " [fused]\n" : " [not fused]\n");
+    }
+    for (int mu = 0; mu < p->d; ++mu) {
+      long sv, rv;
+      mode_view(p->d, p->n, mu, &sv, &rv);
+      const TuneKey k = p->precision == EXPINT_PREC_SLICED ? sliced_key(sv, p->n[mu], rv)
+                                                            : mode_product_key(p->dtype == EXPINT_C128, sv, p->n[mu], rv);
+      s += "mode " + std::to_string(mu + 1) + ": " + tune_describe(k) + "\n";
+    }
+  } else {
+    s = "reduced-precision mu-mode products: one configuration\n";
+  }
+  if (needed) *needed = s.size() + 1;
+  if (len > 0) {
+    const size_t m = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), m);
+    buf[m] = '\0';
+  }
   return EXPINT_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "../../include/expint.h"
 
@@ -18,6 +19,52 @@ int phi_setup_method(int method, bool cplx, int n, const double* A, int lda, dou
                      int ldo);
 // keep this thread's phi_setup calls on one host thread (callers that already parallelise)
 void phi_setup_single_threaded(bool on);
+
+// ---------------------------------------------------------------------------
+// launch-configuration tuning (the autotuner, tune.hip)
+// ---------------------------------------------------------------------------
+
+// A family is a kernel whose launch configuration (tile shape, waves, pipeline
+// depth; for modes 1 and 2 also "not fused") has several candidates, all of
+// which compute the same sums in the same order; a key is one launch shape.
+enum TuneFamily : int {
+  TUNE_MP_REAL = 0,  // FP64 mu-mode product, real data     key (M, Q, K, batches)
+  TUNE_MP_CPLX = 1,  // FP64 mu-mode product, complex data  key (M, Q, K, batches)
+  TUNE_SLICED = 2,   // exact-slice int8 product            key (M, Q, Kpad, batches)
+  TUNE_MODES12 = 3,  // modes 1 and 2 in one launch         key (n1, n2, r, 0); last candidate = not fused
+  TUNE_FAMILIES = 4
+};
+struct TuneKey {
+  int family = 0;
+  long a = 0, b = 0, c = 0, d = 0;
+};
+int tune_candidate_count(int family);
+const char* tune_candidate_name(int family, int i);
+// The candidate a launch of shape k uses: one forced by the tuner on this
+// thread, else the environment override of the family (EXPINT_TILE,
+// EXPINT_SLICE_TILE, EXPINT_M12), else the tuned choice, else -1 (the
+// launcher's own measured default).
+int tune_choice(const TuneKey& k);
+// The tuned choice of k alone (-1 if none).
+int tune_lookup(const TuneKey& k);
+// Keys of the launches the kernels make for a mu-mode product of a tensor viewed
+// as (s, n, r), and for modes 1 and 2 of an n1 x n2 x r stack.
+TuneKey mode_product_key(bool cplx, long s, int n, long r);
+TuneKey sliced_key(long s, int n, long r);
+TuneKey modes12_key(int n1, int n2, long r);
+// Tunes every launch a Tucker operator of this shape, element type and
+// contraction precision makes (all modes present), on scratch tensors;
+// synchronous, allocates and frees its scratch.
+int tune_tucker_shapes(int d, const int* n, int dtype, int precision, void* stream);
+// "family a b c d: candidate (tuned, us)" or ": default" for one key
+std::string tune_describe(const TuneKey& k);
+// Candidate names of each family (defined next to the kernels).
+int mode_product_tile_count();
+const char* mode_product_tile_name(int i);
+int sliced_tile_count();
+const char* sliced_tile_name(int i);
+int modes12_shape_count();
+const char* modes12_shape_name(int i);
 
 // ---------------------------------------------------------------------------
 // mu-mode product launcher

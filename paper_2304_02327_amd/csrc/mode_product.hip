@@ -333,14 +333,6 @@ const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128",
                                   "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4", "64x64k32"};
 constexpr int kNumTiles = sizeof(kTileNames) / sizeof(kTileNames[0]);
 
-int tile_override() {
-  const char* e = std::getenv("EXPINT_TILE");
-  if (!e) return -1;
-  for (int i = 0; i < kNumTiles; ++i)
-    if (std::strcmp(e, kTileNames[i]) == 0) return i;
-  return -1;
-}
-
 // Measured on MI355X (FP64, K = n): 128x64 outputs on 8 waves is the fastest
 // real tile from 128^3 to 384^3 (69% of the FP64 MFMA peak at 384^3); complex
 // data, with four MFMAs per output block, does best on 64x64 / 8 waves.
@@ -349,8 +341,9 @@ int tile_override() {
 // on 8 waves, unless that leaves fewer than two tiles per CU (256 CUs); then
 // 64 x 64 on 4 waves, whose twice as many workgroups overlap each other's
 // prologue and store burst (128^3: 15.2 instead of 15.8 us per launch).
-int choose_tile(bool cplx, long M, long Q, long batches) {
-  const int o = tile_override();
+// The autotuner's choice (or EXPINT_TILE) comes first.
+int choose_tile(bool cplx, long M, long Q, long K, long batches) {
+  const int o = tune_choice(TuneKey{cplx ? TUNE_MP_CPLX : TUNE_MP_REAL, M, Q, K, batches});
   if (o >= 0) return o;
   if (cplx) return M >= 64 ? 6 : 2;
   if (M >= 128) {
@@ -364,7 +357,7 @@ int choose_tile(bool cplx, long M, long Q, long batches) {
 template <typename T, bool BK>
 int launch_choice(GemmArgs& g, hipStream_t st) {
   constexpr int KCR = std::is_same<T, cdouble>::value ? 8 : 16;
-  switch (choose_tile(std::is_same<T, cdouble>::value, g.M, g.Q, g.batches)) {
+  switch (choose_tile(std::is_same<T, cdouble>::value, g.M, g.Q, g.K, g.batches)) {
     case 1: return launch_tile<T, BK, 64, 32, KCR, 2, 2>(g, st);
     case 2: return launch_tile<T, BK, 32, 64, KCR, 2, 2>(g, st);
     case 3: return launch_tile<T, BK, 128, 64, KCR, 2, 2>(g, st);
@@ -386,6 +379,16 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
 }
 
 }  // namespace
+
+int mode_product_tile_count() { return kNumTiles; }
+const char* mode_product_tile_name(int i) { return i >= 0 && i < kNumTiles ? kTileNames[i] : "?"; }
+
+// the GEMM launch_mode_product makes: mode 1 (s == 1) is M = n, Q = r, one batch;
+// modes >= 2 are M = s, Q = n, r batches; K = n either way
+TuneKey mode_product_key(bool cplx, long s, int n, long r) {
+  if (s == 1) return TuneKey{cplx ? TUNE_MP_CPLX : TUNE_MP_REAL, n, r, n, 1};
+  return TuneKey{cplx ? TUNE_MP_CPLX : TUNE_MP_REAL, s, n, n, r};
+}
 
 int grouped_tile_shape(int* tm, int* tq) {
   *tm = 64;

@@ -244,21 +244,24 @@ __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
 
 bool modes12_fits(int n1, int n2) { return n1 >= 1 && n1 <= kModes12MaxN1 && n2 >= 1 && n2 <= kModes12MaxN2; }
 
+TuneKey modes12_key(int n1, int n2, long r) { return TuneKey{TUNE_MODES12, n1, n2, r, 0}; }
+
 namespace {
 
 // Workgroup shapes (rows x waves); EXPINT_M12 set to a name overrides the default.
 const char* const kShapeNames[] = {"r32w4", "r32w8", "r16w4", "r64w8", "r64w16"};
 constexpr int kRows[] = {32, 32, 16, 64, 64};
+constexpr int kNumShapes = sizeof(kRows) / sizeof(kRows[0]);
 
 // Measured on MI355X (ETD2RK steps, FP64): at 128^3 the fused launch takes
 // 26.6 us with 64 rows on 16 waves, 28.0 us with 32 rows on 8 waves and 29.0 us
 // with 32 rows on 4 waves; at 80 x 81 x 82, where 64-row tiles give fewer
 // workgroups than CUs, 32 rows on 8 waves is fastest.
-int shape_choice(int n1, long r) {
-  const char* e = std::getenv("EXPINT_M12");
-  if (e)
-    for (int i = 0; i < (int)(sizeof(kShapeNames) / sizeof(kShapeNames[0])); ++i)
-      if (std::strcmp(e, kShapeNames[i]) == 0) return i;
+// The autotuner's choice (or EXPINT_M12) comes first; its "not fused" candidate
+// is decided before this launcher is called.
+int shape_choice(int n1, int n2, long r) {
+  const int c = tune_choice(modes12_key(n1, n2, r));
+  if (c >= 0 && c < kNumShapes) return c;
   return (n1 + 63) / 64 * r >= 256 ? 4 : 1;
 }
 
@@ -275,13 +278,16 @@ void launch_shape(int shape, long nt, hipStream_t st, const Modes12Args& g) {
 
 }  // namespace
 
+int modes12_shape_count() { return kNumShapes; }
+const char* modes12_shape_name(int i) { return i >= 0 && i < kNumShapes ? kShapeNames[i] : "?"; }
+
 int launch_modes12(int n1, int n2, long r, const void* M1, const void* M2, const void* V, const Epilogue& epi,
                    void* stream) {
   if (r <= 0) return EXPINT_OK;
   if (!modes12_fits(n1, n2))
     return set_error(EXPINT_EINVAL, "fused modes 1 and 2: n1 = %d, n2 = %d outside 1..%d, 1..%d", n1, n2,
                      kModes12MaxN1, kModes12MaxN2);
-  const int shape = shape_choice(n1, r);
+  const int shape = shape_choice(n1, n2, r);
   Modes12Args g;
   g.M1 = static_cast<const double*>(M1);
   g.M2 = static_cast<const double*>(M2);

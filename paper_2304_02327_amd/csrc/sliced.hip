@@ -517,14 +517,6 @@ const char* const kSliceTileNames[] = {"64x64w4k64s2o2", "128x64w8k64s2o1", "64x
                                        "64x64w4k32s2o3", "64x64w4k32s4o2",  "128x64w8k32s4o1"};
 constexpr int kNumSliceTiles = sizeof(kSliceTileNames) / sizeof(kSliceTileNames[0]);
 
-int slice_tile_override() {
-  const char* e = std::getenv("EXPINT_SLICE_TILE");
-  if (!e) return -1;
-  for (int i = 0; i < kNumSliceTiles; ++i)
-    if (std::strcmp(e, kSliceTileNames[i]) == 0) return i;
-  return -1;
-}
-
 template <int WGM, int WGQ, int KC, int S, int OCC>
 int launch_gemm_tile(SliceGemmArgs& g, hipStream_t st) {
   constexpr int TM = 32 * WGM, TQ = 32 * WGQ;
@@ -540,8 +532,9 @@ int launch_gemm_tile(SliceGemmArgs& g, hipStream_t st) {
   return EXPINT_OK;
 }
 
+// The autotuner's choice (or EXPINT_SLICE_TILE) comes first.
 int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
-  int choice = slice_tile_override();
+  int choice = tune_choice(TuneKey{TUNE_SLICED, g.M, g.Q, g.Kpad, g.batches});
   if (choice < 0) choice = 0;
   switch (choice) {
     case 1: return launch_gemm_tile<4, 2, 64, 2, 1>(g, st);
@@ -556,6 +549,15 @@ int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
 }  // namespace
 
 int slice_kpad(int n) { return (n + 63) / 64 * 64; }
+
+int sliced_tile_count() { return kNumSliceTiles; }
+const char* sliced_tile_name(int i) { return i >= 0 && i < kNumSliceTiles ? kSliceTileNames[i] : "?"; }
+
+// the GEMM launch_sliced_mode_product makes (mode 1 when s == 1)
+TuneKey sliced_key(long s, int n, long r) {
+  if (s == 1) return TuneKey{TUNE_SLICED, n, r, slice_kpad(n), 1};
+  return TuneKey{TUNE_SLICED, s, n, slice_kpad(n), r};
+}
 
 size_t slice_digits_bytes(long rows, int n) {
   const size_t plane = (size_t)rows * (size_t)slice_kpad(n);
