@@ -175,6 +175,7 @@ int tucker_apply_noalloc(int d, const int* n, const void* const* M, const void* 
 /*
  * tucker_tune -- the autotuner: times every candidate launch configuration
  * (tile shape, waves, pipeline depth, modes 1 and 2 in one launch or two) of
+ * the FP64, FP32, bf16x3 and exact-slice mu-mode products, for
  * every launch a tucker_apply of this shape, element type and precision (all
  * modes present) makes, on scratch operands of the same sizes (hashed values), and
  * keeps the fastest per launch shape and device architecture for the rest of
@@ -184,9 +185,10 @@ int tucker_apply_noalloc(int d, const int* n, const void* const* M, const void* 
  * appended, so a later process makes the same choices.  The candidates of a
  * launch compute the same sums in the same order, so results do not depend on
  * the choice.  Environment overrides (EXPINT_TILE, EXPINT_SLICE_TILE,
- * EXPINT_M12) still take precedence.  Synchronous; allocates and frees its
- * scratch (about three tensors).  FP32 and bf16x3 have one configuration each
- * (nothing to tune).  Errors: EINVAL, ENOTSUP (as tucker_apply), ENOMEM, EHIP.
+ * EXPINT_M12, EXPINT_LP_TILE) still take precedence.  Synchronous; allocates and frees its
+ * scratch (about three tensors).  Complex data contracted in FP32 (complex64)
+ * has one configuration (nothing to tune).  Errors: EINVAL, ENOTSUP (as
+ * tucker_apply), ENOMEM, EHIP.
  */
 int tucker_tune(int d, const int* n, int dtype, int precision, void* stream);
 

@@ -889,8 +889,14 @@ extern "C" int expint_plan_describe(const expint_plan* p, char* buf, size_t len,
                                                             : mode_product_key(p->dtype == EXPINT_C128, sv, p->n[mu], rv);
       s += "mode " + std::to_string(mu + 1) + ": " + tune_describe(k) + "\n";
     }
+  } else if (p->dtype == EXPINT_F64) {
+    for (int mu = 0; mu < p->d; ++mu) {
+      long sv, rv;
+      mode_view(p->d, p->n, mu, &sv, &rv);
+      s += "mode " + std::to_string(mu + 1) + ": " + tune_describe(lp_key(p->precision, sv, p->n[mu], rv)) + "\n";
+    }
   } else {
-    s = "reduced-precision mu-mode products: one configuration\n";
+    s = "complex64 mu-mode products: one configuration\n";
   }
   if (needed) *needed = s.size() + 1;
   if (len > 0) {

@@ -32,7 +32,9 @@ enum TuneFamily : int {
   TUNE_MP_CPLX = 1,  // FP64 mu-mode product, complex data  key (M, Q, K, batches)
   TUNE_SLICED = 2,   // exact-slice int8 product            key (M, Q, Kpad, batches)
   TUNE_MODES12 = 3,  // modes 1 and 2 in one launch         key (n1, n2, r, 0); last candidate = not fused
-  TUNE_FAMILIES = 4
+  TUNE_LP_FP32 = 4,  // FP32 mu-mode product (real data)    key (M, Q, K, batches)
+  TUNE_LP_BF16X3 = 5,  // bf16x3 mu-mode product            key (M, Q, K, batches)
+  TUNE_FAMILIES = 6
 };
 struct TuneKey {
   int family = 0;
@@ -52,6 +54,7 @@ int tune_lookup(const TuneKey& k);
 TuneKey mode_product_key(bool cplx, long s, int n, long r);
 TuneKey sliced_key(long s, int n, long r);
 TuneKey modes12_key(int n1, int n2, long r);
+TuneKey lp_key(int precision, long s, int n, long r);
 // Tunes every launch a Tucker operator of this shape, element type and
 // contraction precision makes (all modes present), on scratch tensors;
 // synchronous, allocates and frees its scratch.
@@ -65,6 +68,8 @@ int sliced_tile_count();
 const char* sliced_tile_name(int i);
 int modes12_shape_count();
 const char* modes12_shape_name(int i);
+int lp_tile_count(int precision);
+const char* lp_tile_name(int precision, int i);
 
 // ---------------------------------------------------------------------------
 // mu-mode product launcher

@@ -906,22 +906,52 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs
   });
 }
 
-template <int PREC, typename TA, typename TB, bool OUT32, bool BK>
-int launch_lp_typed(GemmArgs& g, hipStream_t s) {
-  // FP32: 128x64 on 8 waves (as FP64); BF16X3: 64x64 on 4 waves (the hi/lo split
-  // needs the registers of two prefetched chunks of 8-element groups)
-  constexpr int TM = PREC == EXPINT_PREC_FP32 ? 128 : 64, TQ = 64;
+template <int PREC, typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int WGM, int WGQ>
+int launch_lp_tile(GemmArgs& g, hipStream_t s) {
   set_tile_counts(g, TM, TQ);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
   if constexpr (PREC == EXPINT_PREC_FP32)
-    hipLaunchKernelGGL((k_mode_product_f32<TA, TB, OUT32, BK, TM, TQ, 16, 4, 2>), dim3((unsigned)nt), dim3(512), 0, s, g);
+    hipLaunchKernelGGL((k_mode_product_f32<TA, TB, OUT32, BK, TM, TQ, 16, WGM, WGQ>), dim3((unsigned)nt),
+                       dim3(64 * WGM * WGQ), 0, s, g);
   else
-    hipLaunchKernelGGL((k_mode_product_bf16x3<TA, TB, OUT32, BK, TM, TQ, 2, 2>), dim3((unsigned)nt), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_mode_product_bf16x3<TA, TB, OUT32, BK, TM, TQ, WGM, WGQ>), dim3((unsigned)nt),
+                       dim3(64 * WGM * WGQ), 0, s, g);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
+}
+
+// Tile shapes of the reduced-precision products (TMxTQ outputs, w = waves; "t":
+// the waves split the tile 2 x 4 instead of 4 x 2).  bf16x3 stages one 8-element
+// K group per thread and chunk, so TM and TQ are at least half the thread count.
+const char* const kF32TileNames[] = {"128x64w8", "64x64w4", "128x128w8", "128x128w16", "256x128w16"};
+const char* const kBf16TileNames[] = {"64x64w4", "128x128w8", "128x128w8t", "256x128w8", "128x256w8t"};
+constexpr int kNumF32Tiles = 5, kNumBf16Tiles = 5;
+
+// The autotuner's choice (or EXPINT_LP_TILE) comes first; defaults: FP32
+// 128x64 on 8 waves (as FP64), bf16x3 64x64 on 4 waves.
+template <int PREC, typename TA, typename TB, bool OUT32, bool BK>
+int launch_lp_typed(GemmArgs& g, hipStream_t s) {
+  const int c = tune_choice(TuneKey{PREC == EXPINT_PREC_FP32 ? TUNE_LP_FP32 : TUNE_LP_BF16X3, g.M, g.Q, g.K, g.batches});
+  if constexpr (PREC == EXPINT_PREC_FP32) {
+    switch (c) {
+      case 1: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 64, 64, 2, 2>(g, s);
+      case 2: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 128, 4, 2>(g, s);
+      case 3: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 128, 4, 4>(g, s);
+      case 4: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 256, 128, 4, 4>(g, s);
+      default: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 64, 4, 2>(g, s);
+    }
+  } else {
+    switch (c) {
+      case 1: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 128, 4, 2>(g, s);
+      case 2: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 128, 2, 4>(g, s);
+      case 3: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 256, 128, 4, 2>(g, s);
+      case 4: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 128, 256, 2, 4>(g, s);
+      default: return launch_lp_tile<PREC, TA, TB, OUT32, BK, 64, 64, 2, 2>(g, s);
+    }
+  }
 }
 
 // V (FP64 or FP32) and M (FP64) in; out0 FP32 (plain store) or the FP64 epilogue.
@@ -959,6 +989,18 @@ int launch_c64(bool v32, GemmArgs& g, bool mode1, hipStream_t s) {
 }
 
 }  // namespace
+
+int lp_tile_count(int precision) { return precision == EXPINT_PREC_FP32 ? kNumF32Tiles : kNumBf16Tiles; }
+const char* lp_tile_name(int precision, int i) {
+  if (i < 0 || i >= lp_tile_count(precision)) return "?";
+  return precision == EXPINT_PREC_FP32 ? kF32TileNames[i] : kBf16TileNames[i];
+}
+
+TuneKey lp_key(int precision, long s, int n, long r) {
+  const int fam = precision == EXPINT_PREC_FP32 ? TUNE_LP_FP32 : TUNE_LP_BF16X3;
+  if (s == 1) return TuneKey{fam, n, r, n, 1};
+  return TuneKey{fam, s, n, n, r};
+}
 
 int launch_mode_product_lp(int precision, bool cplx, bool v32, bool out32, long s, int n, long r, const void* M,
                            const void* V, const Epilogue& epi, void* stream) {

@@ -53,8 +53,9 @@ std::mutex g_tune_mutex;  // one tuning run at a time (timings must not overlap)
 thread_local int t_forced_family = -1;
 thread_local int t_forced_choice = -1;
 
-const char* const kFamilyTags[TUNE_FAMILIES] = {"mp_real", "mp_cplx", "sliced", "modes12"};
-const char* const kFamilyEnv[TUNE_FAMILIES] = {"EXPINT_TILE", "EXPINT_TILE", "EXPINT_SLICE_TILE", "EXPINT_M12"};
+const char* const kFamilyTags[TUNE_FAMILIES] = {"mp_real", "mp_cplx", "sliced", "modes12", "lp_fp32", "lp_bf16x3"};
+const char* const kFamilyEnv[TUNE_FAMILIES] = {"EXPINT_TILE", "EXPINT_TILE", "EXPINT_SLICE_TILE", "EXPINT_M12",
+                                               "EXPINT_LP_TILE", "EXPINT_LP_TILE"};
 
 // gcnArchName of the current device (cached per device ordinal)
 std::string device_arch() {
@@ -126,6 +127,8 @@ int tune_candidate_count(int family) {
     case TUNE_MP_CPLX: return mode_product_tile_count();
     case TUNE_SLICED: return sliced_tile_count();
     case TUNE_MODES12: return modes12_shape_count() + 1;
+    case TUNE_LP_FP32: return lp_tile_count(EXPINT_PREC_FP32);
+    case TUNE_LP_BF16X3: return lp_tile_count(EXPINT_PREC_BF16X3);
     default: return 0;
   }
 }
@@ -136,6 +139,8 @@ const char* tune_candidate_name(int family, int i) {
     case TUNE_MP_CPLX: return mode_product_tile_name(i);
     case TUNE_SLICED: return sliced_tile_name(i);
     case TUNE_MODES12: return i == modes12_shape_count() ? "off" : modes12_shape_name(i);
+    case TUNE_LP_FP32: return lp_tile_name(EXPINT_PREC_FP32, i);
+    case TUNE_LP_BF16X3: return lp_tile_name(EXPINT_PREC_BF16X3, i);
     default: return "?";
   }
 }
@@ -231,9 +236,10 @@ int tune_key(const TuneKey& k, hipStream_t st, const std::function<int()>& launc
 // Synchronous; allocates and frees its scratch.
 int tune_tucker_shapes(int d, const int* n, int dtype, int precision, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (precision != EXPINT_PREC_FP64 && precision != EXPINT_PREC_SLICED) return EXPINT_OK;  // one configuration
-  std::lock_guard<std::mutex> serial(g_tune_mutex);
   const bool cplx = dtype == EXPINT_C128;
+  const bool lp = precision == EXPINT_PREC_FP32 || precision == EXPINT_PREC_BF16X3;
+  if (lp && cplx) return EXPINT_OK;  // complex64 products have one configuration
+  std::lock_guard<std::mutex> serial(g_tune_mutex);
   const size_t es = cplx ? 16 : 8;
   long N = 1;
   int nmax = 1;
@@ -275,7 +281,14 @@ int tune_tucker_shapes(int d, const int* n, int dtype, int precision, void* stre
     long s = 1, r = 1;
     for (int k = 0; k < mu; ++k) s *= n[k];
     for (int k = mu + 1; k < d; ++k) r *= n[k];
-    if (precision == EXPINT_PREC_SLICED) {
+    if (lp) {
+      // as in a chain: the first mode reads FP64, the inner ones FP32, the last one
+      // returns FP64 (timed with a plain store)
+      const bool v32 = mu > 0, out32 = mu + 1 < d;
+      rc = tune_key(lp_key(precision, s, n[mu], r), st, [&]() {
+        return launch_mode_product_lp(precision, false, v32, out32, s, n[mu], r, Mm, X, plain, st);
+      });
+    } else if (precision == EXPINT_PREC_SLICED) {
       rc = launch_slice(static_cast<const double*>(Mm), n[mu], n[mu], 1, false, mdig, st);
       if (rc == EXPINT_OK) rc = launch_slice(static_cast<const double*>(X), s, n[mu], r, mu == 0, dig, st);
       if (rc == EXPINT_OK)

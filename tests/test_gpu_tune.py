@@ -82,12 +82,32 @@ def test_every_slice_tile_gives_the_same_bits(monkeypatch):
         assert torch.equal(got, ref), t
 
 
-@pytest.mark.parametrize("precision", ["fp64", "slice"])
+LP_TILES = {"fp32": ["128x64w8", "64x64w4", "128x128w8", "128x128w16", "256x128w16"],
+            "bf16x3": ["64x64w4", "128x128w8", "128x128w8t", "256x128w8", "128x256w8t"]}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_every_reduced_precision_tile_gives_the_same_bits(precision, monkeypatch):
+    """Ragged sizes around every tile (FP64 first mode, FP32 inner mode, FP64 last mode)."""
+    n = (37, 300, 133)
+    ref, V, Ms = _apply(n, 13, precision)
+    err = rel_inf(px.tensor_from_device(ref), tucker(V, Ms))
+    assert 1e-17 < err <= (1e-5 if precision == "fp32" else 1e-4)
+    for t in LP_TILES[precision]:
+        monkeypatch.setenv("EXPINT_LP_TILE", t)
+        got, _, _ = _apply(n, 13, precision)
+        assert torch.equal(got, ref), t
+
+
+TOL = {"fp64": 1e-13, "slice": 1e-10, "fp32": 1e-5, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "slice", "fp32", "bf16x3"])
 def test_tuned_tucker_matches_oracle(precision):
     n = (48, 100, 36)
     px.tucker_tune(list(n), precision=precision)
     got, V, Ms = _apply(n, 11, precision)
-    assert rel_inf(px.tensor_from_device(got), tucker(V, Ms)) <= (1e-13 if precision == "fp64" else 1e-10)
+    assert rel_inf(px.tensor_from_device(got), tucker(V, Ms)) <= TOL[precision]
 
 
 def test_tuned_plan_equals_forced_plan_bitwise(monkeypatch):
