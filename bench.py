@@ -554,6 +554,8 @@ def bench_kernel_only(args):
     torch.cuda.set_device(dev)
     p, _ = make_workload(args.workload)
     U0 = px.tensor_to_device(p.u0, device=dev)
+    # the launch configurations a plan of this workload would use
+    px.tucker_tune(list(p.n), px.C128 if p.is_complex else px.F64, args.precision)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     r = tucker_roofline(args, p, px, dev, stream, U0, args.precision, args.workload)
