@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libexpint.so")
 
 HIP_SOURCES = ["api.hip", "mode_product.hip", "pointwise.hip", "riccati.hip", "sliced.hip", "small.hip", "modes12.hip",
                "tune.hip"]
-CXX_SOURCES = ["phi_setup.cpp"]
+CXX_SOURCES = ["phi_setup.cpp", "host_abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [

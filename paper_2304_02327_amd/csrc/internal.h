@@ -12,6 +12,19 @@ namespace expint {
 // records a thread-local message and returns `code`
 int set_error(int code, const char* fmt, ...);
 
+// Argument checks shared by the entry points (host_abi.cpp): the total N of a
+// shape (d <= 4, every n >= 1, N < 2^31), the operand limits of the kernels
+// (each tensor below 2 GiB; exact slice: n_mu <= kSliceMaxK and digit planes
+// below 2 GiB), whether a precision code is known, and the workspace layout of
+// tucker_apply (ping-pong tensors, the tensor digits of the largest mode, the
+// digits of every M).
+int validate_shape(int d, const int* n, long* N);
+int check_operand_limits(int d, const int* n, long N, int dtype, int precision);
+bool valid_precision(int precision);
+int tucker_ws_layout(int d, const int* n, long N, int dtype, int precision, int modes, size_t* tensors,
+                     size_t* digits, size_t* mdigits);
+size_t sliced_tensor_digits_bytes(int d, const int* n, long N);
+
 int phi_setup_real(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
 int phi_setup_complex(int n, const double* A, int lda, double tau, int ell_max, double* out, int ldo);
 // phi_0..phi_ell_max of tau A by EXPINT_PHI_TAYLOR or EXPINT_PHI_QUAD (complex: interleaved)

@@ -548,7 +548,6 @@ int launch_gemm(SliceGemmArgs& g, hipStream_t st) {
 
 }  // namespace
 
-int slice_kpad(int n) { return (n + 63) / 64 * 64; }
 
 int sliced_tile_count() { return kNumSliceTiles; }
 const char* sliced_tile_name(int i) { return i >= 0 && i < kNumSliceTiles ? kSliceTileNames[i] : "?"; }
@@ -559,10 +558,6 @@ TuneKey sliced_key(long s, int n, long r) {
   return TuneKey{TUNE_SLICED, s, n, slice_kpad(n), r};
 }
 
-size_t slice_digits_bytes(long rows, int n) {
-  const size_t plane = (size_t)rows * (size_t)slice_kpad(n);
-  return ((size_t)kDigits * plane + 255) / 256 * 256 + ((size_t)rows * sizeof(int) + 255) / 256 * 256;
-}
 
 int launch_slice(const double* V, long s, int n, long r, bool contiguous, void* out, void* stream) {
   const int Kpad = slice_kpad(n);
