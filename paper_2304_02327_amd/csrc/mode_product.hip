@@ -32,6 +32,7 @@ namespace expint {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
   const void* A;  // Aop[m, k] = A[m + lda k] (+ batch * sA)
@@ -735,7 +736,9 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);   // exact difference in FP32, rounded to nearest even
 }
 
-template <typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int WGM, int WGQ>
+// BV (with BK): a column of Bop starts on a 16-byte boundary, so each thread's
+// 8 consecutive K values load as 16-byte vectors (values past K are zeroed).
+template <typename TA, typename TB, bool OUT32, bool BK, int TM, int TQ, int WGM, int WGQ, bool BV = false>
 __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs g) {
   constexpr int NT = 64 * WGM * WGQ;
   constexpr int KC = 32;                   // one MFMA K step per chunk
@@ -799,7 +802,25 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product_bf16x3(GemmArgs
       for (int e = 0; e < 8; ++e) ra[p][e] = buffer_ld_s<TA>(ra_src, va[p], lda * (unsigned)(k0 + e) * SA);
 #pragma unroll
     for (int p = 0; p < BG; ++p) {
-      if constexpr (BK) {
+      if constexpr (BK && BV) {
+        const int kg = (tid + NT * p) % (KC / 8);
+        constexpr int PER = 16 / SB;  // elements per 16-byte load
+#pragma unroll
+        for (int v = 0; v < 8 / PER; ++v) {
+          const v4i w = __builtin_bit_cast(
+              v4i, __builtin_amdgcn_raw_buffer_load_b128(rb_src, (int)(vb[p] + 16u * v), (int)(k0 * SB), 0));
+#pragma unroll
+          for (int e = 0; e < PER; ++e) {
+            TB x;
+            if constexpr (SB == 4)
+              x = __builtin_bit_cast(float, w[e]);
+            else
+              x = __builtin_bit_cast(double, (unsigned long long)(unsigned)w[2 * e] |
+                                                 ((unsigned long long)(unsigned)w[2 * e + 1] << 32));
+            rb[p][PER * v + e] = (k0 + 8 * kg + PER * v + e < Ki) ? x : TB(0);
+          }
+        }
+      } else if constexpr (BK) {
         const int kg = (tid + NT * p) % (KC / 8);
 #pragma unroll
         for (int e = 0; e < 8; ++e)
@@ -914,6 +935,9 @@ int launch_lp_tile(GemmArgs& g, hipStream_t s) {
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
   if constexpr (PREC == EXPINT_PREC_FP32)
     hipLaunchKernelGGL((k_mode_product_f32<TA, TB, OUT32, BK, TM, TQ, 16, WGM, WGQ>), dim3((unsigned)nt),
+                       dim3(64 * WGM * WGQ), 0, s, g);
+  else if (BK && (g.bq * (long)sizeof(TB)) % 16 == 0)
+    hipLaunchKernelGGL((k_mode_product_bf16x3<TA, TB, OUT32, BK, TM, TQ, WGM, WGQ, BK>), dim3((unsigned)nt),
                        dim3(64 * WGM * WGQ), 0, s, g);
   else
     hipLaunchKernelGGL((k_mode_product_bf16x3<TA, TB, OUT32, BK, TM, TQ, WGM, WGQ>), dim3((unsigned)nt),
