@@ -217,6 +217,10 @@ def bench_riccati(args, scheme="etd2rk"):
     N = batch.state_size
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
+    t = time.perf_counter()
+    if not args.no_tune:
+        batch.tune(U, stream=stream)  # each phase's grouped tile scheme (U is left as it is)
+    tune_s = time.perf_counter() - t
     with torch.cuda.stream(stream):
         batch.run(U, args.warmup, use_graph=True, stream=stream)
     stream.synchronize()
@@ -243,7 +247,8 @@ def bench_riccati(args, scheme="etd2rk"):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"64 Riccati-type instances, n1,n2 ~ U{{32..512}}, {name} phisplit, FP64, tau=1e-3",
                    "dof": N, "graph": True, "launches_per_step": launches},
-        "wall_s_timed_region": wall, "phi_setup_s": setup_s,
+        "wall_s_timed_region": wall, "phi_setup_s": setup_s, "tune_s": round(tune_s, 3),
+        "launch_configuration": batch.describe().splitlines(),
         "roofline": {"kernel": f"k_grouped_gemm ({launches} persistent FP64 MFMA launches per step)",
                      "bound": "mfma", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
@@ -576,6 +581,8 @@ def main():
                     help="contraction precision of the mu-mode products for a single workload "
                          "(state and phi stay FP64); the default sweep runs all four")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched workloads: keep the default (or EXPINT_GROUPED) grouped tile scheme")
     ap.add_argument("--cpu-seconds", type=float, default=22.0)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only time the dominant kernel of --workload/--precision (for PMC passes)")

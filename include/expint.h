@@ -372,6 +372,32 @@ int expint_batch_step(expint_batch_plan* plan, double* U, void* ws, void* stream
 int expint_batch_run(expint_batch_plan* plan, double* U, int nsteps, int use_graph, void* ws, void* stream);
 
 /*
+ * expint_batch_tune -- the autotuner for the batched engine: each step is a
+ * fixed sequence of grouped launches (one per phase), and each launch can put
+ * its GEMMs on one tile class (64 x 64 outputs) or on two classes in the same
+ * persistent launch (128 x 64 or 128 x 128 outputs for the large GEMMs).  This
+ * times every grouped tile scheme on every phase, starting from one step of a
+ * private copy of U (device, packed state, left unchanged; ws as for
+ * expint_batch_step), and keeps the fastest per phase for the rest of the
+ * process (and in EXPINT_TUNE_CACHE, as tucker_tune does).  Later steps of this
+ * plan, and of plans with the same scheme and instance sizes, use the choice;
+ * EXPINT_GROUPED (a scheme name) overrides it.  Every scheme computes the same
+ * sums in the same order, so results do not depend on the choice.  The plan's
+ * status words are restored.  Synchronous; allocates a copy of the state and
+ * the descriptor lists, and frees them.  Errors: EINVAL (NULL or misaligned
+ * arguments), ENOMEM, EHIP.
+ */
+int expint_batch_tune(expint_batch_plan* plan, double* U, void* ws, void* stream);
+
+/*
+ * expint_batch_describe -- one line per phase: "phase k: <scheme used> [<what
+ * the autotuner holds for it>]".  Writes at most len bytes (NUL-terminated) to
+ * buf (may be NULL) and the full size including the NUL to *needed (may be
+ * NULL).  Errors: EINVAL (NULL plan), ENOMEM.
+ */
+int expint_batch_describe(const expint_batch_plan* plan, char* buf, size_t len, size_t* needed);
+
+/*
  * expint_batch_status -- waits for `stream`, then reports what the steps
  * enqueued since the previous call found, and clears it:
  *   EXPINT_ENUMERIC   a Rosenbrock-Euler Jacobian direction needed more

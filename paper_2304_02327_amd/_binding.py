@@ -79,6 +79,8 @@ def _load():
     lib.expint_batch_workspace_size.argtypes = [c_void_p, ctypes.POINTER(c_size_t)]
     lib.expint_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     lib.expint_batch_run.argtypes = [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]
+    lib.expint_batch_tune.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.expint_batch_describe.argtypes = [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]
     lib.expint_batch_plan_destroy.argtypes = [c_void_p]
     lib.expint_batch_plan_destroy.restype = None
     lib.expint_last_error.restype = ctypes.c_char_p
@@ -97,7 +99,8 @@ EXPORTED_SYMBOLS = (
     "expint_version",
     "expint_riccati_plan_create", "expint_riccati_plan_create_ex", "expint_batch_state_size",
     "expint_batch_workspace_size",
-    "expint_batch_step", "expint_batch_run", "expint_batch_status", "expint_batch_plan_destroy",
+    "expint_batch_step", "expint_batch_run", "expint_batch_status", "expint_batch_tune", "expint_batch_describe",
+    "expint_batch_plan_destroy",
 )
 
 
@@ -472,6 +475,20 @@ class RiccatiBatch:
         _check(lib.expint_batch_run(self._handle, U.data_ptr(), int(nsteps), 1 if use_graph else 0,
                                     self.ws.data_ptr(), _stream_handle(stream)))
         return U
+
+    def tune(self, U, stream=None):
+        """Time every grouped tile scheme on every phase (from one step of a copy
+        of U; U itself is unchanged) and keep the fastest (expint_batch_tune)."""
+        self._check_state(U)
+        _check(lib.expint_batch_tune(self._handle, U.data_ptr(), self.ws.data_ptr(), _stream_handle(stream)))
+
+    def describe(self) -> str:
+        """The grouped tile scheme of each phase (expint_batch_describe)."""
+        need = ctypes.c_size_t(0)
+        _check(lib.expint_batch_describe(self._handle, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.expint_batch_describe(self._handle, buf, need.value, None))
+        return buf.value.decode()
 
     def status(self, U=None, stream=None) -> int:
         """What the steps since the last call found (waits for the stream): OK,

@@ -3,7 +3,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/expint.h"
 
@@ -47,7 +49,8 @@ enum TuneFamily : int {
   TUNE_MODES12 = 3,  // modes 1 and 2 in one launch         key (n1, n2, r, 0); last candidate = not fused
   TUNE_LP_FP32 = 4,  // FP32 mu-mode product (real data)    key (M, Q, K, batches)
   TUNE_LP_BF16X3 = 5,  // bf16x3 mu-mode product            key (M, Q, K, batches)
-  TUNE_FAMILIES = 6
+  TUNE_GROUPED = 6,  // grouped tile scheme of a batched phase  key (scheme/phase, count, total, size hash)
+  TUNE_FAMILIES = 7
 };
 struct TuneKey {
   int family = 0;
@@ -62,6 +65,10 @@ const char* tune_candidate_name(int family, int i);
 int tune_choice(const TuneKey& k);
 // The tuned choice of k alone (-1 if none).
 int tune_lookup(const TuneKey& k);
+// Times every candidate of k's family (each call of `launch` makes the launches
+// of the candidate tune_choice(k) returns while it runs) and keeps the fastest;
+// a key tuned before is not timed again.
+int tune_key(const TuneKey& k, void* stream, const std::function<int()>& launch);
 // Keys of the launches the kernels make for a mu-mode product of a tensor viewed
 // as (s, n, r), and for modes 1 and 2 of an n1 x n2 x r stack.
 TuneKey mode_product_key(bool cplx, long s, int n, long r);
@@ -149,7 +156,20 @@ size_t gemm_desc_size();
 int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
                    long ldc, const Epilogue& epi, const int* gate = nullptr, int gate_level = 0);
 long gemm_desc_tiles(const void* desc);
-int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
+// Grouped tile schemes (which GEMMs of a launch take the larger tile class):
+// set a descriptor's class and tile counts for a scheme (make_gemm_desc sets scheme 0).
+int grouped_scheme_count();
+const char* grouped_scheme_name(int i);
+void gemm_desc_set_scheme(void* desc, int scheme);
+// Workgroup b of a grouped launch runs tile `tile` of descriptor `desc` (none if desc < 0).
+struct GroupedBlock {
+  int desc, tile;
+};
+// The map of `count` consecutive descriptors (host): each GEMM's tiles on one XCD.
+void grouped_block_map(const void* descs, int count, std::vector<GroupedBlock>& map);
+bool grouped_block_map_valid(const void* descs, int count, const std::vector<GroupedBlock>& map);
+// descs and map (blocks entries) in device memory; every descriptor follows `scheme`.
+int launch_grouped_gemm(bool bk_contiguous, const void* descs, const GroupedBlock* map, long blocks, int scheme,
                         void* stream);
 
 // Fused time stepping of a small two-dimensional FP64 problem (n1, n2 <= 64):

@@ -20,9 +20,11 @@
 // combination and the next stage's g.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "device_common.h"
 #include "internal.h"
@@ -47,6 +49,8 @@ struct GemmArgs {
   const int* gate = nullptr;  // grouped launches: tiles run only while *gate > gate_level
   int gate_level = 0;
   int m_fastest = 0;  // tile order, set with the tile counts (tile_coord)
+  int cls = 0;        // grouped launches: tile class (0 small, 1 large) and its tile shape
+  int tile_m = 64, tile_q = 64;
 };
 
 // Bop is shared by all batches, Aop only when sA == 0: the M tile runs fastest
@@ -74,10 +78,24 @@ __device__ __forceinline__ cdouble buffer_ld<cdouble>(__amdgpu_buffer_rsrc_t r, 
   return __builtin_bit_cast(cdouble, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
 }
 
+// LDS of one tile: two buffers of the A chunk (KC x TM) and of the B chunk
+// (KC x TQ, padded by one column when stored transposed), per real plane.
+template <typename T, bool BK, int TM, int TQ, int KC>
+constexpr int tile_lds_doubles() {
+  return 2 * (std::is_same<T, cdouble>::value ? 2 : 1) * KC * (TM + (BK ? TQ + 1 : TQ));
+}
+
+// The LDS of a kernel's tiles: every tile function of one kernel that names the
+// same size shares one allocation (tile classes of the grouped launch).
+template <int N>
+__shared__ double lds_pool[N];
+
 // One TM x TQ output tile (tile index T_ in [0, tiles_m tiles_q batches)) of the
-// GEMM described by g, computed by the whole workgroup.  Used by the single
-// launch below and by the persistent grouped launch.
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2>
+// GEMM described by g, computed by the whole workgroup in lds_pool<LDSN>
+// (at least tile_lds_doubles entries).  Used by the single launch below and by
+// the persistent grouped launch, whose tile classes share one LDS allocation.
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2,
+          int LDSN = tile_lds_doubles<T, BK, TM, TQ, KC>()>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   constexpr bool CPLX = std::is_same<T, cdouble>::value;
   constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
@@ -91,8 +109,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   static_assert(AL * NT == TM * KC && BL * NT == TQ * KC, "tile / thread mismatch");
   static_assert(FM >= 1 && FQ >= 1 && WM % 16 == 0 && WQ % 16 == 0 && KC % 4 == 0, "bad tile");
 
-  __shared__ double As[2][NP][KC * LDA_S];
-  __shared__ double Bs[2][NP][KC * LDB_S];
+  static_assert(LDSN >= tile_lds_doubles<T, BK, TM, TQ, KC>(), "LDS pool too small");
+  // A chunk buffer b, plane p at lds_pool[(b NP + p) KC LDA_S], the B chunks after all of them
+  auto As = [](int b, int p, int i) -> double& { return lds_pool<LDSN>[(b * NP + p) * (KC * LDA_S) + i]; };
+  auto Bs = [](int b, int p, int i) -> double& {
+    return lds_pool<LDSN>[2 * NP * KC * LDA_S + (b * NP + p) * (KC * LDB_S) + i];
+  };
 
   const TileCoord tc = tile_coord(T_, g.tiles_m, g.tiles_q, g.m_fastest);
   const long tm = tc.tm, tq = tc.tq, b = tc.b;
@@ -163,10 +185,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
       const int idx = tid + NT * p;
       const int m = idx % TM, k = idx / TM;
       if constexpr (CPLX) {
-        As[buf][0][k * LDA_S + m] = ra[p].re;
-        As[buf][1][k * LDA_S + m] = ra[p].im;
+        As(buf, 0, k * LDA_S + m) = ra[p].re;
+        As(buf, 1, k * LDA_S + m) = ra[p].im;
       } else {
-        As[buf][0][k * LDA_S + m] = ra[p];
+        As(buf, 0, k * LDA_S + m) = ra[p];
       }
     }
 #pragma unroll
@@ -175,10 +197,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
       const int q = BK ? idx / KC : idx % TQ;
       const int k = BK ? idx % KC : idx / TQ;
       if constexpr (CPLX) {
-        Bs[buf][0][k * LDB_S + q] = rb[p].re;
-        Bs[buf][1][k * LDB_S + q] = rb[p].im;
+        Bs(buf, 0, k * LDB_S + q) = rb[p].re;
+        Bs(buf, 1, k * LDB_S + q) = rb[p].im;
       } else {
-        Bs[buf][0][k * LDB_S + q] = rb[p];
+        Bs(buf, 0, k * LDB_S + q) = rb[p];
       }
     }
   };
@@ -189,9 +211,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[p][i] = As[cur][p][(kk + lk) * LDA_S + wm0 + i * 16 + lr];
+        for (int i = 0; i < FM; ++i) af[p][i] = As(cur, p, (kk + lk) * LDA_S + wm0 + i * 16 + lr);
 #pragma unroll
-        for (int j = 0; j < FQ; ++j) bf[p][j] = Bs[cur][p][(kk + lk) * LDB_S + wq0 + j * 16 + lr];
+        for (int j = 0; j < FQ; ++j) bf[p][j] = Bs(cur, p, (kk + lk) * LDB_S + wq0 + j * 16 + lr);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
@@ -291,26 +313,41 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
   gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ, PF>(g, xcd_remap((long)blockIdx.x, nt));
 }
 
-// Persistent grouped GEMM: `count` independent GEMMs (one descriptor each,
-// tiles_m/tiles_q filled in, listed in decreasing cost) share one launch.
-// Tile t belongs to the descriptor i with start[i] <= t < start[i + 1]; each
-// workgroup walks t = blockIdx.x, blockIdx.x + gridDim.x, ... so the costly
-// tiles at the front are spread over every workgroup (longest first).
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ>
-__global__ __launch_bounds__(64 * WGM * WGQ) void k_grouped_gemm(const GemmArgs* __restrict__ descs,
-                                                                 const long* __restrict__ start, int count) {
-  const long total = start[count];
-  for (long t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = count - 1;  // last i with start[i] <= t
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (start[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const GemmArgs g = descs[lo];
-    if (g.gate && *g.gate <= g.gate_level) continue;  // uniform over the workgroup
-    __syncthreads();  // the previous tile's last LDS reads are done before this tile's stores
-    gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ>(g, t - start[lo]);
+// Tile classes of the persistent grouped launch: TM x TQ outputs, K chunks of
+// KC, WGM x WGQ waves (512 threads in every class).
+template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_>
+struct TileCfg {
+  static constexpr int TM = TM_, TQ = TQ_, KC = KC_, WGM = WGM_, WGQ = WGQ_, NT = 64 * WGM_ * WGQ_;
+};
+using GSmall = TileCfg<64, 64, 32, 2, 4>;
+using GSmall4 = TileCfg<64, 64, 16, 2, 2>;
+using GBig = TileCfg<128, 64, 16, 4, 2>;
+using GHuge = TileCfg<128, 128, 16, 4, 2>;
+
+// Grouped GEMM: independent GEMMs (one descriptor each, tile class and tile
+// counts filled in) share one launch.  Workgroup b runs tile map[b].tile of
+// descriptor map[b].desc (none if desc < 0); the host builds the map so that
+// each GEMM's tiles run on one XCD (grouped_block_map).  A descriptor of class
+// 1 runs on L tiles, class 0 on S tiles; both use one LDS allocation (the
+// larger of the two).
+template <bool BK, class S, class L>
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_grouped_gemm(
+    const GemmArgs* __restrict__ descs, const GroupedBlock* __restrict__ map) {
+  constexpr int LS = tile_lds_doubles<double, BK, S::TM, S::TQ, S::KC>();
+  constexpr int LL = tile_lds_doubles<double, BK, L::TM, L::TQ, L::KC>();
+  constexpr int LN = LS > LL ? LS : LL;
+  static_assert(S::NT == L::NT, "both tile classes run on the same waves");
+  const GroupedBlock e = map[blockIdx.x];
+  if (e.desc < 0) return;
+  const GemmArgs g = descs[e.desc];
+  if (g.gate && *g.gate <= g.gate_level) return;  // uniform over the workgroup
+  if constexpr (std::is_same<S, L>::value) {
+    gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN>(g, e.tile);
+  } else {
+    if (g.cls)
+      gemm_tile<double, BK, L::TM, L::TQ, L::KC, L::WGM, L::WGQ, 2, LN>(g, e.tile);
+    else
+      gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN>(g, e.tile);
   }
 }
 
@@ -391,24 +428,70 @@ TuneKey mode_product_key(bool cplx, long s, int n, long r) {
   return TuneKey{cplx ? TUNE_MP_CPLX : TUNE_MP_REAL, s, n, n, r};
 }
 
-int grouped_tile_shape(int* tm, int* tq) {
-  *tm = 64;
-  *tq = 64;
-  return EXPINT_OK;
+// Grouped tile schemes: which tile class each GEMM of a grouped launch takes.
+//   "64x64"          every GEMM on 64 x 64 tiles (K chunks of 32)
+//   "64x64+128x64"   GEMMs with M >= 128 on 128 x 64 tiles (K chunks of 16), the rest 64 x 64
+//   "128x64"         every GEMM on 128 x 64 tiles
+//   "64x64+128x128"  GEMMs with M, Q >= 128 on 128 x 128 tiles, the rest 64 x 64
+//   "64x64w4"        every GEMM on 64 x 64 tiles of 4 waves (K chunks of 16; four workgroups per CU)
+// EXPINT_GROUPED set to one of these names overrides the tuned choice.
+const char* const kGroupedNames[] = {"64x64", "64x64+128x64", "128x64", "64x64+128x128", "64x64w4"};
+constexpr int kNumGrouped = sizeof(kGroupedNames) / sizeof(kGroupedNames[0]);
+
+int grouped_scheme_count() { return kNumGrouped; }
+const char* grouped_scheme_name(int i) { return i >= 0 && i < kNumGrouped ? kGroupedNames[i] : "?"; }
+
+// the class (0 small, 1 large) and tile shape of an M x Q GEMM under a scheme
+static int grouped_class(int scheme, long M, long Q, int* tm, int* tq) {
+  int cls = 0;
+  switch (scheme) {
+    case 1: cls = M >= 128; break;
+    case 2: cls = 1; break;
+    case 3: cls = M >= 128 && Q >= 128; break;
+    default: cls = 0;
+  }
+  *tm = cls ? 128 : 64;
+  *tq = (cls && scheme == 3) ? 128 : 64;
+  return cls;
 }
 
-int launch_grouped_gemm(bool bk_contiguous, const void* descs, const long* start, int count, long total_tiles,
+void gemm_desc_set_scheme(void* desc, int scheme) {
+  GemmArgs g;
+  std::memcpy(&g, desc, sizeof(g));
+  int tm, tq;
+  g.cls = grouped_class(scheme, g.M, g.Q, &tm, &tq);
+  g.tile_m = tm;
+  g.tile_q = tq;
+  set_tile_counts(g, tm, tq);
+  std::memcpy(desc, &g, sizeof(g));
+}
+
+template <bool BK, class S, class L>
+static void launch_grouped_typed(long grid, const GemmArgs* d, const GroupedBlock* map, hipStream_t st) {
+  hipLaunchKernelGGL((k_grouped_gemm<BK, S, L>), dim3((unsigned)grid), dim3(S::NT), 0, st, d, map);
+}
+
+template <bool BK>
+static void launch_grouped_scheme(int scheme, long grid, const GemmArgs* d, const GroupedBlock* map, hipStream_t st) {
+  switch (scheme) {
+    case 1: return launch_grouped_typed<BK, GSmall, GBig>(grid, d, map, st);
+    case 2: return launch_grouped_typed<BK, GBig, GBig>(grid, d, map, st);
+    case 3: return launch_grouped_typed<BK, GSmall, GHuge>(grid, d, map, st);
+    case 4: return launch_grouped_typed<BK, GSmall4, GSmall4>(grid, d, map, st);
+    default: return launch_grouped_typed<BK, GSmall, GSmall>(grid, d, map, st);
+  }
+}
+
+int launch_grouped_gemm(bool bk_contiguous, const void* descs, const GroupedBlock* map, long blocks, int scheme,
                         void* stream) {
-  if (count <= 0 || total_tiles <= 0) return EXPINT_OK;
+  if (blocks <= 0) return EXPINT_OK;
+  if (blocks > 0x7fffffffL) return set_error(EXPINT_EINVAL, "grouped GEMM: too many workgroups (%ld)", blocks);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const long grid = total_tiles < 2048 ? total_tiles : 2048;
   const GemmArgs* d = static_cast<const GemmArgs*>(descs);
   if (bk_contiguous)
-    hipLaunchKernelGGL((k_grouped_gemm<double, true, 64, 64, 32, 2, 4>), dim3((unsigned)grid), dim3(512), 0, st, d,
-                       start, count);
+    launch_grouped_scheme<true>(scheme, blocks, d, map, st);
   else
-    hipLaunchKernelGGL((k_grouped_gemm<double, false, 64, 64, 32, 2, 4>), dim3((unsigned)grid), dim3(512), 0, st, d,
-                       start, count);
+    launch_grouped_scheme<false>(scheme, blocks, d, map, st);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "grouped GEMM launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
@@ -418,8 +501,6 @@ size_t gemm_desc_size() { return sizeof(GemmArgs); }
 
 int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,
                    long ldc, const Epilogue& epi, const int* gate, int gate_level) {
-  int tm, tq;
-  grouped_tile_shape(&tm, &tq);
   GemmArgs g;
   g.A = A;
   g.lda = lda;
@@ -436,9 +517,95 @@ int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, l
   g.epi = epi;
   g.gate = gate;
   g.gate_level = gate_level;
+  int tm, tq;
+  g.cls = grouped_class(0, M, Q, &tm, &tq);
+  g.tile_m = tm;
+  g.tile_q = tq;
   set_tile_counts(g, tm, tq);
   std::memcpy(out, &g, sizeof(g));
   return EXPINT_OK;
+}
+
+// The workgroup -> tile map of a grouped launch.  Workgroups are dispatched to
+// the XCDs in turn (b mod 8), and each XCD has its own L2, so the tiles of one
+// GEMM, which re-read each other's operand panels, are kept on one XCD: the
+// GEMMs (split into runs of at most a sixteenth of all tiles, so that no XCD
+// holds much more than its share) go to the XCDs longest first, each to the
+// XCD with the least work so far (work = tiles x TM TQ (K + 64), the 64
+// standing for the prologue and the epilogue); within an XCD the runs keep
+// that order.  XCD x's j-th tile becomes workgroup 8 j + x; a workgroup past
+// the end of its XCD's list has desc = -1.  EXPINT_GROUPED_FLAT=1 gives the
+// plain order (tile t on workgroup t) instead.
+void grouped_block_map(const void* descs, int count, std::vector<GroupedBlock>& map) {
+  constexpr int X = 8;
+  const GemmArgs* d = static_cast<const GemmArgs*>(descs);
+  std::vector<long> tiles(count);
+  long total = 0;
+  for (int i = 0; i < count; ++i) {
+    GemmArgs g;
+    std::memcpy(&g, d + i, sizeof(g));
+    tiles[i] = g.tiles_m * g.tiles_q * g.batches;
+    total += tiles[i];
+  }
+  map.clear();
+  if (const char* e = std::getenv("EXPINT_GROUPED_FLAT"); e && std::strcmp(e, "1") == 0) {
+    for (int i = 0; i < count; ++i)
+      for (long t = 0; t < tiles[i]; ++t) map.push_back(GroupedBlock{i, (int)t});
+    return;
+  }
+  struct Run {
+    int desc;
+    long t0, t1;
+    double work;
+  };
+  const long cap = std::max(1L, (total + 15) / 16);
+  std::vector<Run> runs;
+  for (int i = 0; i < count; ++i) {
+    GemmArgs g;
+    std::memcpy(&g, d + i, sizeof(g));
+    const double per = (double)g.tile_m * g.tile_q * (double)(g.K + 64);
+    for (long t0 = 0; t0 < tiles[i]; t0 += cap) {
+      const long t1 = std::min(tiles[i], t0 + cap);
+      runs.push_back(Run{i, t0, t1, per * (double)(t1 - t0)});
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.work > b.work; });
+  std::vector<std::vector<GroupedBlock>> lists(X);
+  double load[X] = {0};
+  for (const Run& r : runs) {
+    int x = 0;
+    for (int k = 1; k < X; ++k)
+      if (load[k] < load[x]) x = k;
+    load[x] += r.work;
+    for (long t = r.t0; t < r.t1; ++t) lists[x].push_back(GroupedBlock{r.desc, (int)t});
+  }
+  size_t longest = 0;
+  for (const auto& l : lists) longest = std::max(longest, l.size());
+  map.assign(longest * X, GroupedBlock{-1, 0});
+  for (int x = 0; x < X; ++x)
+    for (size_t j = 0; j < lists[x].size(); ++j) map[j * X + x] = lists[x][j];
+}
+
+// Every tile of every descriptor exactly once, nothing out of range.
+bool grouped_block_map_valid(const void* descs, int count, const std::vector<GroupedBlock>& map) {
+  const GemmArgs* d = static_cast<const GemmArgs*>(descs);
+  std::vector<long> base(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    GemmArgs g;
+    std::memcpy(&g, d + i, sizeof(g));
+    base[i + 1] = base[i] + g.tiles_m * g.tiles_q * g.batches;
+  }
+  std::vector<char> seen(base[count], 0);
+  for (const GroupedBlock& e : map) {
+    if (e.desc < 0) continue;
+    if (e.desc >= count || e.tile < 0 || e.tile >= base[e.desc + 1] - base[e.desc]) return false;
+    char& f = seen[base[e.desc] + e.tile];
+    if (f) return false;
+    f = 1;
+  }
+  for (char f : seen)
+    if (!f) return false;
+  return true;
 }
 
 long gemm_desc_tiles(const void* desc) {

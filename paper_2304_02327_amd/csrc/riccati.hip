@@ -48,6 +48,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -160,17 +161,19 @@ struct expint_batch_plan {
   // descriptors for the current (U, ws): one grouped launch per phase
   struct Phase {
     bool bk;                  // B operand contiguous along k
-    long first, start_off;    // first descriptor, offset of its tile prefix sums
+    long first;               // first descriptor
     int ndesc;
     long tiles;
+    int scheme;               // grouped tile scheme (grouped_scheme_name)
+    long map_off, blocks;     // its workgroup -> tile map (grouped_block_map)
   };
   std::vector<Phase> phases;
   int prep_after = -1;        // the phi prep kernel runs after this phase
   void* ddesc = nullptr;
-  long* dstart = nullptr;
+  GroupedBlock* dmap = nullptr;
   PhiJob* djobs = nullptr;
   int* dstatus = nullptr;     // two status words (kStatus*)
-  size_t desc_cap = 0, start_cap = 0;
+  size_t desc_cap = 0, map_cap = 0;
   const void* d_U = nullptr;
   const void* d_ws = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -185,7 +188,7 @@ void free_batch(expint_batch_plan* p) {
   if (p->djobs) (void)hipFree(p->djobs);
   if (p->dstatus) (void)hipFree(p->dstatus);
   if (p->ddesc) (void)hipFree(p->ddesc);
-  if (p->dstart) (void)hipFree(p->dstart);
+  if (p->dmap) (void)hipFree(p->dmap);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
 }
 
@@ -202,21 +205,40 @@ Epilogue linear(void* out, double alpha, const void* in1 = nullptr, double beta 
   return e;
 }
 
-// Descriptor lists of the phases, built on the host.
+// The autotuner's key of phase k of a plan: the scheme, the number of squaring
+// phases, the phase, and the instance sizes (count, total, and a hash of the list).
+TuneKey grouped_key(const expint_batch_plan* p, int k) {
+  unsigned long long h = 1469598103934665603ull;  // FNV-1a over the sizes
+  for (int i = 0; i < p->count; ++i)
+    for (int v : {p->n1[i], p->n2[i]}) {
+      h ^= (unsigned)v;
+      h *= 1099511628211ull;
+    }
+  const long a = (p->scheme == EXPINT_ROSENBROCK_EULER ? 1000000L : 0L) + 1000L * p->smax + k;
+  return TuneKey{TUNE_GROUPED, a, p->count, p->total, (long)(h >> 2)};
+}
+
+// Descriptor lists of the phases, built on the host.  Phase k's tiles follow
+// the grouped tile scheme `force` (>= 0), else the tuned choice of its key,
+// else scheme 0.
 struct PhaseBuilder {
+  const expint_batch_plan* plan;
+  int force;
   size_t dsz = gemm_desc_size();
   std::vector<char> desc;
-  std::vector<long> start;
+  std::vector<GroupedBlock> map;
   std::vector<expint_batch_plan::Phase> phases;
+  PhaseBuilder(const expint_batch_plan* p, int forced_scheme = -1) : plan(p), force(forced_scheme) {}
   char* open(bool bk) {  // a new phase
     expint_batch_plan::Phase ph;
     ph.bk = bk;
     ph.first = (long)(desc.size() / dsz);
-    ph.start_off = (long)start.size();
     ph.ndesc = 0;
     ph.tiles = 0;
+    ph.map_off = 0;
+    ph.blocks = 0;
+    ph.scheme = force >= 0 ? force : std::max(0, tune_choice(grouped_key(plan, (int)phases.size())));
     phases.push_back(ph);
-    start.push_back(0);
     return nullptr;
   }
   char* add() {  // room for one more descriptor of the open phase
@@ -225,9 +247,21 @@ struct PhaseBuilder {
   }
   void added() {  // after make_gemm_desc filled the last descriptor
     auto& ph = phases.back();
-    ph.tiles += gemm_desc_tiles(desc.data() + desc.size() - dsz);
+    char* d = desc.data() + desc.size() - dsz;
+    gemm_desc_set_scheme(d, ph.scheme);
+    ph.tiles += gemm_desc_tiles(d);
     ph.ndesc += 1;
-    start.push_back(ph.tiles);
+  }
+  bool finish() {  // every phase's workgroup map, after the last descriptor
+    std::vector<GroupedBlock> m;
+    for (auto& ph : phases) {
+      grouped_block_map(desc.data() + (size_t)ph.first * dsz, ph.ndesc, m);
+      if (!grouped_block_map_valid(desc.data() + (size_t)ph.first * dsz, ph.ndesc, m)) return false;
+      ph.map_off = (long)map.size();
+      ph.blocks = (long)m.size();
+      map.insert(map.end(), m.begin(), m.end());
+    }
+    return true;
   }
 };
 
@@ -413,10 +447,7 @@ void build_rosenbrock(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& p
   }
 }
 
-// Build every phase's descriptors for state U and workspace ws and upload them.
-int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
-  PhaseBuilder pb;
-  std::vector<PhiJob> jobs;
+int build_phases(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb, std::vector<PhiJob>& jobs) {
   if (p->scheme == EXPINT_ROSENBROCK_EULER) {
     build_rosenbrock(p, U, ws, pb, jobs);
     p->prep_after = 2;
@@ -424,13 +455,30 @@ int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
     build_etd2rk(p, U, ws, pb);
     p->prep_after = -1;
   }
+  if (!pb.finish()) return set_error(EXPINT_EINVAL, "internal error: a grouped workgroup map misses or repeats a tile");
+  return EXPINT_OK;
+}
+
+// Build every phase's descriptors for state U and workspace ws and upload them.
+int build_descriptors(expint_batch_plan* p, double* U, char* ws) {
+  PhaseBuilder pb(p);
+  std::vector<PhiJob> jobs;
+  if (const int rc = build_phases(p, U, ws, pb, jobs); rc != EXPINT_OK) return rc;
   // descriptors of an earlier (U, ws) pair may still be read by enqueued work
   if (p->d_U && hipDeviceSynchronize() != hipSuccess)
     return set_error(EXPINT_EHIP, "device synchronisation before a descriptor rebuild failed");
-  if (pb.desc.size() > p->desc_cap || pb.start.size() > p->start_cap)
-    return set_error(EXPINT_EINVAL, "batched descriptors exceed the plan's capacity");
+  if (pb.desc.size() > p->desc_cap) return set_error(EXPINT_EINVAL, "batched descriptors exceed the plan's capacity");
+  if (pb.map.size() > p->map_cap) {  // the maps' size depends on the tuned tile schemes
+    if (p->dmap) (void)hipFree(p->dmap);
+    p->dmap = nullptr;
+    p->map_cap = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&p->dmap), pb.map.size() * sizeof(GroupedBlock)) != hipSuccess)
+      return set_error(EXPINT_ENOMEM, "device allocation for the workgroup maps failed");
+    p->map_cap = pb.map.size();
+  }
   if (hipMemcpy(p->ddesc, pb.desc.data(), pb.desc.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->dstart, pb.start.data(), pb.start.size() * sizeof(long), hipMemcpyHostToDevice) != hipSuccess ||
+      (!pb.map.empty() && hipMemcpy(p->dmap, pb.map.data(), pb.map.size() * sizeof(GroupedBlock),
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
       (!jobs.empty() &&
        hipMemcpy(p->djobs, jobs.data(), jobs.size() * sizeof(PhiJob), hipMemcpyHostToDevice) != hipSuccess))
     return set_error(EXPINT_EHIP, "upload of batched GEMM descriptors failed");
@@ -449,7 +497,7 @@ int enqueue_batch_step(expint_batch_plan* p, hipStream_t s) {
   for (size_t k = 0; k < p->phases.size(); ++k) {
     const auto& ph = p->phases[k];
     const char* d = static_cast<const char*>(p->ddesc) + (size_t)ph.first * dsz;
-    const int rc = launch_grouped_gemm(ph.bk, d, p->dstart + ph.start_off, ph.ndesc, ph.tiles, s);
+    const int rc = launch_grouped_gemm(ph.bk, d, p->dmap + ph.map_off, ph.blocks, ph.scheme, s);
     if (rc != EXPINT_OK) return rc;
     if ((int)k == p->prep_after) {
       hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(64 * kPrepWaves), 0, s, p->djobs, p->smax,
@@ -594,14 +642,13 @@ int riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const
   };
   upload(&p->dA1, hA1);
   upload(&p->dA2, hA2);
-  size_t ndesc = 0, nphase = 0;
+  size_t ndesc = 0;
   if (!ros) {
     upload(&p->dP1a, hP1a);
     upload(&p->dP2a, hP2a);
     upload(&p->dP1b, hP1b);
     upload(&p->dP2b, hP2b);
     ndesc = (size_t)kPhases * count;
-    nphase = kPhases;
   } else {
     // A2^T, the matrices by decreasing size, and the number of squaring phases:
     // the largest count ||tau A_mu||_1 needs, plus 4 for the U B terms of the
@@ -636,14 +683,11 @@ int riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const
       return na > nb;
     });
     ndesc = (size_t)count * (32 + 4 * p->smax);
-    nphase = 18 + p->smax;
     if (rc == EXPINT_OK && hipMalloc(reinterpret_cast<void**>(&p->djobs), 2 * count * sizeof(PhiJob)) != hipSuccess)
       rc = set_error(EXPINT_ENOMEM, "device allocation for phi jobs failed");
   }
   p->desc_cap = ndesc * gemm_desc_size();
-  p->start_cap = ndesc + nphase;
-  if (rc == EXPINT_OK && (hipMalloc(&p->ddesc, p->desc_cap) != hipSuccess ||
-                          hipMalloc(reinterpret_cast<void**>(&p->dstart), p->start_cap * sizeof(long)) != hipSuccess))
+  if (rc == EXPINT_OK && hipMalloc(&p->ddesc, p->desc_cap) != hipSuccess)
     rc = set_error(EXPINT_ENOMEM, "device allocation for descriptors failed");
   if (rc == EXPINT_OK) {
     if (hipMalloc(reinterpret_cast<void**>(&p->dstatus), 2 * sizeof(int)) != hipSuccess)
@@ -760,6 +804,124 @@ extern "C" int expint_batch_status(expint_batch_plan* p, const double* U, void* 
     return set_error(EXPINT_ENUMERIC, "a Jacobian direction needed more than the plan's %d squarings: its phi_1 is "
                      "inaccurate", p->smax);
   if (st[kStatusNonFinite]) return set_error(EXPINT_ENONFINITE, "the state or a Jacobian direction is not finite");
+  return EXPINT_OK;
+}
+
+namespace {
+
+// Times every grouped tile scheme on every phase of the plan and keeps the
+// fastest per phase (the autotuner's table; EXPINT_TUNE_CACHE keeps it across
+// processes).  The steps run on a private copy of U in ws; the caller's U and
+// the plan's status words are left as they were.
+int batch_tune(expint_batch_plan* p, double* U, char* ws, hipStream_t s) {
+  const int ns = grouped_scheme_count();
+  const size_t dsz = gemm_desc_size();
+  double* tU = nullptr;
+  std::vector<void*> dd(ns, nullptr);
+  std::vector<GroupedBlock*> dmp(ns, nullptr);
+  std::vector<std::vector<expint_batch_plan::Phase>> ph(ns);
+  int saved[2] = {0, 0};
+  int rc = EXPINT_OK;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(saved, p->dstatus, sizeof(saved), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = set_error(EXPINT_EHIP, "batch tuning: reading the status words failed");
+  if (rc == EXPINT_OK && hipMalloc(reinterpret_cast<void**>(&tU), p->total * sizeof(double)) != hipSuccess)
+    rc = set_error(EXPINT_ENOMEM, "batch tuning: state copy allocation failed");
+  if (rc == EXPINT_OK &&
+      hipMemcpyAsync(tU, U, p->total * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    rc = set_error(EXPINT_EHIP, "batch tuning: state copy failed");
+  // every scheme's descriptors for the copy (scheme 0 also becomes the plan's current set)
+  std::vector<PhiJob> jobs;
+  for (int c = 0; c < ns && rc == EXPINT_OK; ++c) {
+    PhaseBuilder pb(p, c);
+    jobs.clear();
+    if ((rc = build_phases(p, tU, ws, pb, jobs)) != EXPINT_OK) break;
+    ph[c] = pb.phases;
+    if (hipMalloc(&dd[c], pb.desc.size()) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&dmp[c]), std::max<size_t>(1, pb.map.size()) * sizeof(GroupedBlock)) !=
+            hipSuccess) {
+      rc = set_error(EXPINT_ENOMEM, "batch tuning: descriptor allocation failed");
+      break;
+    }
+    if (hipMemcpy(dd[c], pb.desc.data(), pb.desc.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (!pb.map.empty() && hipMemcpy(dmp[c], pb.map.data(), pb.map.size() * sizeof(GroupedBlock),
+                                      hipMemcpyHostToDevice) != hipSuccess) ||
+        (!jobs.empty() && c == 0 &&
+         hipMemcpy(p->djobs, jobs.data(), jobs.size() * sizeof(PhiJob), hipMemcpyHostToDevice) != hipSuccess))
+      rc = set_error(EXPINT_EHIP, "batch tuning: descriptor upload failed");
+  }
+  auto launch_phase = [&](int c, int k) {
+    const auto& q = ph[c][k];
+    return launch_grouped_gemm(q.bk, static_cast<const char*>(dd[c]) + (size_t)q.first * dsz,
+                               dmp[c] + q.map_off, q.blocks, q.scheme, s);
+  };
+  // one whole step first, so that the workspace and the squaring counts hold a step's values
+  const int nph = rc == EXPINT_OK ? (int)ph[0].size() : 0;
+  for (int k = 0; k < nph && rc == EXPINT_OK; ++k) {
+    rc = launch_phase(0, k);
+    if (rc == EXPINT_OK && k == p->prep_after) {
+      hipLaunchKernelGGL(k_phi_prep, dim3(2 * p->count), dim3(64 * kPrepWaves), 0, s, p->djobs, p->smax,
+                         p->dstatus);
+      if (hipGetLastError() != hipSuccess) rc = set_error(EXPINT_EHIP, "batch tuning: phi prep launch failed");
+    }
+  }
+  for (int k = 0; k < nph && rc == EXPINT_OK; ++k) {
+    const TuneKey key = grouped_key(p, k);
+    rc = tune_key(key, s, [&]() { return launch_phase(std::max(0, tune_choice(key)), k); });
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && rc == EXPINT_OK)
+    rc = set_error(EXPINT_EHIP, "batch tuning: synchronisation failed");
+  if (hipMemcpy(p->dstatus, saved, sizeof(saved), hipMemcpyHostToDevice) != hipSuccess && rc == EXPINT_OK)
+    rc = set_error(EXPINT_EHIP, "batch tuning: restoring the status words failed");
+  if (tU) (void)hipFree(tU);
+  for (int c = 0; c < ns; ++c) {
+    if (dd[c]) (void)hipFree(dd[c]);
+    if (dmp[c]) (void)hipFree(dmp[c]);
+  }
+  // the next step rebuilds the descriptors (and the graph) with the tuned schemes
+  p->d_U = nullptr;
+  p->d_ws = nullptr;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int expint_batch_tune(expint_batch_plan* p, double* U, void* ws, void* stream) {
+  if (!p) return set_error(EXPINT_EINVAL, "plan is NULL");
+  if (!U || !ws) return set_error(EXPINT_EINVAL, "U and ws must be non-NULL device pointers");
+  if ((reinterpret_cast<uintptr_t>(U) & 15u) || (reinterpret_cast<uintptr_t>(ws) & 15u))
+    return set_error(EXPINT_EINVAL, "U and ws must be 16-byte aligned");
+  try {
+    return batch_tune(p, U, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "host allocation failed while tuning the batched plan");
+  }
+}
+
+extern "C" int expint_batch_describe(const expint_batch_plan* p, char* buf, size_t len, size_t* needed) {
+  if (!p) return set_error(EXPINT_EINVAL, "plan is NULL");
+  std::string text;
+  try {
+    const int nph = p->scheme == EXPINT_ROSENBROCK_EULER ? 18 + p->smax : kPhases;
+    for (int k = 0; k < nph; ++k) {
+      const TuneKey key = grouped_key(p, k);
+      const int c = tune_choice(key);
+      text += "phase " + std::to_string(k + 1) + ": " + grouped_scheme_name(std::max(0, c)) + " [" +
+              tune_describe(key) + "]\n";
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(EXPINT_ENOMEM, "host allocation failed while describing the batched plan");
+  }
+  if (needed) *needed = text.size() + 1;
+  if (buf && len > 0) {
+    const size_t n = std::min(len - 1, text.size());
+    std::memcpy(buf, text.data(), n);
+    buf[n] = 0;
+  }
   return EXPINT_OK;
 }
 

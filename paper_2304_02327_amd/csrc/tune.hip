@@ -53,9 +53,10 @@ std::mutex g_tune_mutex;  // one tuning run at a time (timings must not overlap)
 thread_local int t_forced_family = -1;
 thread_local int t_forced_choice = -1;
 
-const char* const kFamilyTags[TUNE_FAMILIES] = {"mp_real", "mp_cplx", "sliced", "modes12", "lp_fp32", "lp_bf16x3"};
-const char* const kFamilyEnv[TUNE_FAMILIES] = {"EXPINT_TILE", "EXPINT_TILE", "EXPINT_SLICE_TILE", "EXPINT_M12",
-                                               "EXPINT_LP_TILE", "EXPINT_LP_TILE"};
+const char* const kFamilyTags[TUNE_FAMILIES] = {"mp_real", "mp_cplx",   "sliced", "modes12",
+                                                "lp_fp32", "lp_bf16x3", "grouped"};
+const char* const kFamilyEnv[TUNE_FAMILIES] = {"EXPINT_TILE",    "EXPINT_TILE",    "EXPINT_SLICE_TILE", "EXPINT_M12",
+                                               "EXPINT_LP_TILE", "EXPINT_LP_TILE", "EXPINT_GROUPED"};
 
 // gcnArchName of the current device (cached per device ordinal)
 std::string device_arch() {
@@ -129,6 +130,7 @@ int tune_candidate_count(int family) {
     case TUNE_MODES12: return modes12_shape_count() + 1;
     case TUNE_LP_FP32: return lp_tile_count(EXPINT_PREC_FP32);
     case TUNE_LP_BF16X3: return lp_tile_count(EXPINT_PREC_BF16X3);
+    case TUNE_GROUPED: return grouped_scheme_count();
     default: return 0;
   }
 }
@@ -141,6 +143,7 @@ const char* tune_candidate_name(int family, int i) {
     case TUNE_MODES12: return i == modes12_shape_count() ? "off" : modes12_shape_name(i);
     case TUNE_LP_FP32: return lp_tile_name(EXPINT_PREC_FP32, i);
     case TUNE_LP_BF16X3: return lp_tile_name(EXPINT_PREC_BF16X3, i);
+    case TUNE_GROUPED: return grouped_scheme_name(i);
     default: return "?";
   }
 }
@@ -199,7 +202,8 @@ int time_launch(hipStream_t st, const std::function<int()>& launch, double* us) 
 // call: one launch configuration of that family, as tune_choice forces it) and
 // keeps the fastest (the lower index on a tie).  A key tuned before (in this
 // process or the cache file) is not timed again.
-int tune_key(const TuneKey& k, hipStream_t st, const std::function<int()>& launch) {
+int tune_key(const TuneKey& k, void* stream, const std::function<int()>& launch) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
   if (tune_lookup(k) >= 0) return EXPINT_OK;
   const int nc = tune_candidate_count(k.family);
   int best = -1;
