@@ -315,14 +315,17 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
 
 // Tile classes of the persistent grouped launch: TM x TQ outputs, K chunks of
 // KC, WGM x WGQ waves (512 threads in every class).
-template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_>
+template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_, int WPE_ = 4>
 struct TileCfg {
   static constexpr int TM = TM_, TQ = TQ_, KC = KC_, WGM = WGM_, WGQ = WGQ_, NT = 64 * WGM_ * WGQ_;
+  static constexpr int WPE = WPE_;  // waves per SIMD the kernel's registers must allow
 };
 using GSmall = TileCfg<64, 64, 32, 2, 4>;
 using GSmall4 = TileCfg<64, 64, 16, 2, 2>;
+using GSmall16 = TileCfg<64, 64, 16, 2, 4, 6>;
+using GSmall16x = TileCfg<64, 64, 16, 2, 4, 8>;
 using GBig = TileCfg<128, 64, 16, 4, 2>;
-using GHuge = TileCfg<128, 128, 16, 4, 2>;
+using GBig8 = TileCfg<128, 64, 8, 4, 2, 6>;
 
 // Grouped GEMM: independent GEMMs (one descriptor each, tile class and tile
 // counts filled in) share one launch.  Workgroup b runs tile map[b].tile of
@@ -331,7 +334,7 @@ using GHuge = TileCfg<128, 128, 16, 4, 2>;
 // 1 runs on L tiles, class 0 on S tiles; both use one LDS allocation (the
 // larger of the two).
 template <bool BK, class S, class L>
-__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_grouped_gemm(
+__global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(S::WPE))) void k_grouped_gemm(
     const GemmArgs* __restrict__ descs, const GroupedBlock* __restrict__ map) {
   constexpr int LS = tile_lds_doubles<double, BK, S::TM, S::TQ, S::KC>();
   constexpr int LL = tile_lds_doubles<double, BK, L::TM, L::TQ, L::KC>();
@@ -428,14 +431,20 @@ TuneKey mode_product_key(bool cplx, long s, int n, long r) {
   return TuneKey{cplx ? TUNE_MP_CPLX : TUNE_MP_REAL, s, n, n, r};
 }
 
-// Grouped tile schemes: which tile class each GEMM of a grouped launch takes.
-//   "64x64"          every GEMM on 64 x 64 tiles (K chunks of 32)
-//   "64x64+128x64"   GEMMs with M >= 128 on 128 x 64 tiles (K chunks of 16), the rest 64 x 64
-//   "128x64"         every GEMM on 128 x 64 tiles
-//   "64x64+128x128"  GEMMs with M, Q >= 128 on 128 x 128 tiles, the rest 64 x 64
-//   "64x64w4"        every GEMM on 64 x 64 tiles of 4 waves (K chunks of 16; four workgroups per CU)
-// EXPINT_GROUPED set to one of these names overrides the tuned choice.
-const char* const kGroupedNames[] = {"64x64", "64x64+128x64", "128x64", "64x64+128x128", "64x64w4"};
+// Grouped tile schemes: which tile class each GEMM of a grouped launch takes,
+// and the tile shapes (outputs TM x TQ, K chunk KC, waves, workgroups per CU).
+//   "64x64k16"           every GEMM on 64 x 64 tiles, K chunks of 16, 8 waves, 3 per CU (default)
+//   "64x64k16o4"         the same with registers for 4 workgroups per CU
+//   "64x64"              64 x 64 tiles, K chunks of 32, 8 waves, 2 per CU
+//   "64x64w4"            64 x 64 tiles, K chunks of 16, 4 waves, 4 per CU
+//   "128x64"             every GEMM on 128 x 64 tiles, K chunks of 16, 8 waves, 2 per CU
+//   "128x64k8"           128 x 64 tiles, K chunks of 8, 8 waves, 3 per CU
+//   "64x64+128x64"       GEMMs with M >= 128 on 128 x 64 tiles, the rest 64 x 64 (K chunks 16 / 32)
+//   "64x64k16+128x64k8"  GEMMs with M >= 128 on 128 x 64 tiles (K chunks of 8), the rest 64 x 64 (16)
+// The two-class schemes serve both classes from one launch and one LDS
+// allocation.  EXPINT_GROUPED set to one of these names overrides the tuned choice.
+const char* const kGroupedNames[] = {"64x64k16", "64x64k16o4", "64x64",        "64x64w4",
+                                     "128x64",   "128x64k8",   "64x64+128x64", "64x64k16+128x64k8"};
 constexpr int kNumGrouped = sizeof(kGroupedNames) / sizeof(kGroupedNames[0]);
 
 int grouped_scheme_count() { return kNumGrouped; }
@@ -443,15 +452,17 @@ const char* grouped_scheme_name(int i) { return i >= 0 && i < kNumGrouped ? kGro
 
 // the class (0 small, 1 large) and tile shape of an M x Q GEMM under a scheme
 static int grouped_class(int scheme, long M, long Q, int* tm, int* tq) {
+  (void)Q;
   int cls = 0;
   switch (scheme) {
-    case 1: cls = M >= 128; break;
-    case 2: cls = 1; break;
-    case 3: cls = M >= 128 && Q >= 128; break;
+    case 4:
+    case 5: cls = 1; break;
+    case 6:
+    case 7: cls = M >= 128; break;
     default: cls = 0;
   }
   *tm = cls ? 128 : 64;
-  *tq = (cls && scheme == 3) ? 128 : 64;
+  *tq = 64;
   return cls;
 }
 
@@ -474,11 +485,14 @@ static void launch_grouped_typed(long grid, const GemmArgs* d, const GroupedBloc
 template <bool BK>
 static void launch_grouped_scheme(int scheme, long grid, const GemmArgs* d, const GroupedBlock* map, hipStream_t st) {
   switch (scheme) {
-    case 1: return launch_grouped_typed<BK, GSmall, GBig>(grid, d, map, st);
-    case 2: return launch_grouped_typed<BK, GBig, GBig>(grid, d, map, st);
-    case 3: return launch_grouped_typed<BK, GSmall, GHuge>(grid, d, map, st);
-    case 4: return launch_grouped_typed<BK, GSmall4, GSmall4>(grid, d, map, st);
-    default: return launch_grouped_typed<BK, GSmall, GSmall>(grid, d, map, st);
+    case 1: return launch_grouped_typed<BK, GSmall16x, GSmall16x>(grid, d, map, st);
+    case 2: return launch_grouped_typed<BK, GSmall, GSmall>(grid, d, map, st);
+    case 3: return launch_grouped_typed<BK, GSmall4, GSmall4>(grid, d, map, st);
+    case 4: return launch_grouped_typed<BK, GBig, GBig>(grid, d, map, st);
+    case 5: return launch_grouped_typed<BK, GBig8, GBig8>(grid, d, map, st);
+    case 6: return launch_grouped_typed<BK, GSmall, GBig>(grid, d, map, st);
+    case 7: return launch_grouped_typed<BK, GSmall16, GBig8>(grid, d, map, st);
+    default: return launch_grouped_typed<BK, GSmall16, GSmall16>(grid, d, map, st);
   }
 }
 

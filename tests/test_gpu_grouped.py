@@ -22,7 +22,8 @@ from oracle.norms import rel_inf
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = ["64x64", "64x64+128x64", "128x64", "64x64+128x128", "64x64w4"]
+SCHEMES = ["64x64k16", "64x64k16o4", "64x64", "64x64w4", "128x64", "128x64k8", "64x64+128x64",
+           "64x64k16+128x64k8"]
 
 
 def _instances(seed=41):
@@ -74,7 +75,7 @@ def test_every_grouped_scheme_gives_the_same_bits(scheme, monkeypatch):
         else:
             assert torch.equal(out, ref), name
     # the plain workgroup order instead of the XCD-aware map
-    monkeypatch.setenv("EXPINT_GROUPED", "64x64")
+    monkeypatch.setenv("EXPINT_GROUPED", "64x64k16")
     monkeypatch.setenv("EXPINT_GROUPED_FLAT", "1")
     out, _, _ = _run(insts, scheme, 3)
     assert torch.equal(out, ref)
@@ -83,7 +84,7 @@ def test_every_grouped_scheme_gives_the_same_bits(scheme, monkeypatch):
 @pytest.mark.parametrize("scheme", ["etd2rk", "rosenbrock_euler"])
 def test_tuned_plan_leaves_the_state_and_matches_untuned(scheme, monkeypatch):
     insts = _instances(seed=43)
-    monkeypatch.setenv("EXPINT_GROUPED", "64x64")
+    monkeypatch.setenv("EXPINT_GROUPED", "64x64k16")
     ref, _, _ = _run(insts, scheme, 2)
     monkeypatch.delenv("EXPINT_GROUPED")
     out, got, text = _run(insts, scheme, 2, tune=True)
