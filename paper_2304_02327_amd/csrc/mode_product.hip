@@ -94,8 +94,11 @@ __shared__ double lds_pool[N];
 // GEMM described by g, computed by the whole workgroup in lds_pool<LDSN>
 // (at least tile_lds_doubles entries).  Used by the single launch below and by
 // the persistent grouped launch, whose tile classes share one LDS allocation.
+// IL: in the steady-state loop each chunk's MFMAs are interleaved with its LDS
+// reads, LDS writes and global loads (scheduling groups) instead of the
+// compiler's own order.
 template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2,
-          int LDSN = tile_lds_doubles<T, BK, TM, TQ, KC>()>
+          int LDSN = tile_lds_doubles<T, BK, TM, TQ, KC>(), bool IL = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   constexpr bool CPLX = std::is_same<T, cdouble>::value;
   constexpr int NP = CPLX ? 2 : 1;                  // real planes per element
@@ -242,6 +245,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
     // touching memory), so the outstanding-load count is the same on every
     // path and each store waits only for its own chunk.  One barrier per
     // chunk; the tail (one or two chunks) is peeled.
+    auto interleave = []() {
+      if constexpr (IL) {
+        constexpr int NM = NP * NP * FM * FQ * (KC / 4), NR = NP * (FM + FQ) * (KC / 4);
+        constexpr int RPM = (NR + NM - 1) / NM, NW = NP * (AL + BL), NV = AL + BL;
+#pragma unroll
+        for (int u = 0; u < NM; ++u) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, RPM, 0);  // LDS read
+          if (u < NW) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+          if (u < NV) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global load
+        }
+      }
+    };
     gload(ra[0], rb[0], 0);
     gload(ra[1], rb[1], KC);
     sstore(ra[0], rb[0], 0);
@@ -251,10 +267,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
       gload(ra[0], rb[0], (kc + 2) * KC);
       compute(0);
       sstore(ra[1], rb[1], 1);
+      interleave();
       __syncthreads();
       gload(ra[1], rb[1], (kc + 3) * KC);
       compute(1);
       sstore(ra[0], rb[0], 0);
+      interleave();
       __syncthreads();
     }
     compute(0);  // buffer 0 holds chunk kc, set 1 chunk kc + 1
@@ -307,18 +325,20 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, long T_) {
   });
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF, bool IL>
 __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
   const long nt = g.tiles_m * g.tiles_q * g.batches;
-  gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ, PF>(g, xcd_remap((long)blockIdx.x, nt));
+  gemm_tile<T, BK, TM, TQ, KC, WGM, WGQ, PF, tile_lds_doubles<T, BK, TM, TQ, KC>(), IL>(
+      g, xcd_remap((long)blockIdx.x, nt));
 }
 
 // Tile classes of the persistent grouped launch: TM x TQ outputs, K chunks of
 // KC, WGM x WGQ waves (512 threads in every class).
-template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_, int WPE_ = 4>
+template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_, int WPE_ = 4, bool IL_ = false>
 struct TileCfg {
   static constexpr int TM = TM_, TQ = TQ_, KC = KC_, WGM = WGM_, WGQ = WGQ_, NT = 64 * WGM_ * WGQ_;
   static constexpr int WPE = WPE_;  // waves per SIMD the kernel's registers must allow
+  static constexpr bool IL = IL_;   // interleaved chunk schedule (gemm_tile)
 };
 using GSmall = TileCfg<64, 64, 32, 2, 4>;
 using GSmall4 = TileCfg<64, 64, 16, 2, 2>;
@@ -345,33 +365,36 @@ __global__ __launch_bounds__(S::NT) __attribute__((amdgpu_waves_per_eu(S::WPE)))
   const GemmArgs g = descs[e.desc];
   if (g.gate && *g.gate <= g.gate_level) return;  // uniform over the workgroup
   if constexpr (std::is_same<S, L>::value) {
-    gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN>(g, e.tile);
+    gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN, S::IL>(g, e.tile);
   } else {
     if (g.cls)
-      gemm_tile<double, BK, L::TM, L::TQ, L::KC, L::WGM, L::WGQ, 2, LN>(g, e.tile);
+      gemm_tile<double, BK, L::TM, L::TQ, L::KC, L::WGM, L::WGQ, 2, LN, L::IL>(g, e.tile);
     else
-      gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN>(g, e.tile);
+      gemm_tile<double, BK, S::TM, S::TQ, S::KC, S::WGM, S::WGQ, 2, LN, S::IL>(g, e.tile);
   }
 }
 
-template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2>
+template <typename T, bool BK, int TM, int TQ, int KC, int WGM, int WGQ, int PF = 2, bool IL = false>
 int launch_tile(GemmArgs& g, hipStream_t s) {
   set_tile_counts(g, TM, TQ);
   const long nt = g.tiles_m * g.tiles_q * g.batches;
   if (nt <= 0) return EXPINT_OK;
   if (nt > 0x7fffffffL) return set_error(EXPINT_EINVAL, "mode product: too many tiles (%ld)", nt);
-  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC, WGM, WGQ, PF>), dim3((unsigned)nt), dim3(64 * WGM * WGQ),
+  hipLaunchKernelGGL((k_mode_product<T, BK, TM, TQ, KC, WGM, WGQ, PF, IL>), dim3((unsigned)nt), dim3(64 * WGM * WGQ),
                      0, s, g);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) return set_error(EXPINT_EHIP, "mode product launch failed: %s", hipGetErrorString(err));
   return EXPINT_OK;
 }
 
-// Tile configurations (TM x TQ outputs per workgroup; "w8" = 8 waves, else 4).
-// EXPINT_TILE set to one of these names overrides the automatic choice.
+// Tile configurations (TM x TQ outputs per workgroup; "w8" = 8 waves, else 4;
+// "k32" K chunks of 32; "p3" / "p4" that many register sets in flight; "i" the
+// interleaved chunk schedule).  EXPINT_TILE set to one of these names overrides
+// the automatic choice.
 const char* const kTileNames[] = {"64x64", "64x32", "32x64", "128x64", "64x128", "32x32",
                                   "64x64w8", "128x64w8", "128x128w8", "128x128", "128x64w8k32", "128x128w8k32",
-                                  "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4", "64x64k32"};
+                                  "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4", "64x64k32", "128x64w8i",
+                                  "64x64w8i"};
 constexpr int kNumTiles = sizeof(kTileNames) / sizeof(kTileNames[0]);
 
 // Measured on MI355X (FP64, K = n): 128x64 outputs on 8 waves is the fastest
@@ -415,6 +438,8 @@ int launch_choice(GemmArgs& g, hipStream_t st) {
     case 14: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 3>(g, st);
     case 15: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 4>(g, st);
     case 16: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 2>(g, st);
+    case 17: return launch_tile<T, BK, 128, 64, KCR, 4, 2, 2, true>(g, st);
+    case 18: return launch_tile<T, BK, 64, 64, KCR * 2, 2, 4, 2, true>(g, st);
     default: return launch_tile<T, BK, 64, 64, KCR, 2, 2>(g, st);
   }
 }

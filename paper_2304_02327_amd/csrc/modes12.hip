@@ -42,7 +42,12 @@ __device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t rs, unsigned voff, 
 // NQ: columns of the slab a workgroup covers (n2 <= NQ); RM rows per
 // workgroup; WGM x 4 waves, each owning RM / WGM rows and NQ / 4 columns of T
 // and of the result.
-template <int NQ, int RM, int WGM>
+// SCHED 0: the compiler's instruction order.  1: a wave raises its issue
+// priority while it has MFMAs to issue (s_setprio), so the waves of a SIMD that
+// are staging chunks yield the issue slots to one that multiplies.  2: each
+// chunk's MFMAs are interleaved with its LDS reads, LDS writes and global
+// loads (scheduling groups).
+template <int NQ, int RM, int WGM, int SCHED = 0>
 __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
   constexpr int KC = 16, NW = 4 * WGM, NT = 64 * NW;
   constexpr int WM = RM / WGM, WQ = NQ / 4, FQ = WQ / 16, FM = WM / 16;
@@ -129,13 +134,30 @@ __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
       for (int i = 0; i < FM; ++i) af[i] = As[buf][(kk + lk) * LDA + wm0 + i * 16 + lr];
 #pragma unroll
       for (int j = 0; j < FQ; ++j) bf[j] = Bs[buf][(kk + lk) * LDB + wq0 + j * 16 + lr];
+      if constexpr (SCHED == 1) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FQ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+      if constexpr (SCHED == 1) __builtin_amdgcn_s_setprio(0);
     }
   };
 
+  // SCHED == 2: one chunk's work in a scheduling region, each MFMA followed by
+  // its share of LDS reads, then an LDS write and a global load while they last
+  auto interleave = [](int nvmem, int nwrite) {
+    if constexpr (SCHED == 2) {
+      constexpr int NM = FM * FQ * (KC / 4), NR = (FM + FQ) * (KC / 4);
+      constexpr int RPM = (NR + NM - 1) / NM;
+#pragma unroll
+      for (int u = 0; u < NM; ++u) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, RPM, 0);  // LDS read
+        if (u < nwrite) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+        if (u < nvmem) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global load
+      }
+    }
+  };
   const int nk1 = (n1 + KC - 1) / KC, nk2 = (n2 + KC - 1) / KC;
   double ra[2][AL], rb[2][BL];
   load1(ra[0], rb[0], 0);
@@ -147,10 +169,12 @@ __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
     load1(ra[0], rb[0], kc + 2);
     compute1(0);
     store1(ra[1], rb[1], 1);
+    interleave(AL + BL, AL + BL);
     __syncthreads();
     load1(ra[1], rb[1], kc + 3);
     compute1(1);
     store1(ra[0], rb[0], 0);
+    interleave(AL + BL, AL + BL);
     __syncthreads();
   }
   compute1(0);
@@ -181,10 +205,12 @@ __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
       for (int i = 0; i < FM; ++i) af[i] = Ts[(c * KC + kk + lk) * LDT + wm0 + i * 16 + lr];
 #pragma unroll
       for (int j = 0; j < FQ; ++j) bf[j] = Bs[buf][(kk + lk) * LDB + wq0 + j * 16 + lr];
+      if constexpr (SCHED == 1) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FQ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
+      if constexpr (SCHED == 1) __builtin_amdgcn_s_setprio(0);
     }
   };
 
@@ -209,10 +235,12 @@ __global__ __launch_bounds__(256 * WGM) void k_modes12(Modes12Args g) {
     load2(rb[0], kc + 2);
     compute2(0, kc);
     store2(rb[1], 1);
+    interleave(BL, BL);
     __syncthreads();
     load2(rb[1], kc + 3);
     compute2(1, kc + 1);
     store2(rb[0], 0);
+    interleave(BL, BL);
     __syncthreads();
   }
   compute2(0, kc);
@@ -248,13 +276,16 @@ TuneKey modes12_key(int n1, int n2, long r) { return TuneKey{TUNE_MODES12, n1, n
 
 namespace {
 
-// Workgroup shapes (rows x waves); EXPINT_M12 set to a name overrides the default.
-const char* const kShapeNames[] = {"r32w4", "r32w8", "r16w4", "r64w8", "r64w16"};
-constexpr int kRows[] = {32, 32, 16, 64, 64};
+// Workgroup shapes (rows x waves; "p": s_setprio around the MFMAs, "i": the
+// interleaved chunk schedule); EXPINT_M12 set to a name overrides the default.
+const char* const kShapeNames[] = {"r32w4",   "r32w8",   "r16w4",    "r64w8",    "r64w16",
+                                   "r32w8p", "r32w8i", "r64w16p", "r64w16i"};
+constexpr int kRows[] = {32, 32, 16, 64, 64, 32, 32, 64, 64};
 constexpr int kNumShapes = sizeof(kRows) / sizeof(kRows[0]);
 
-// Measured on MI355X (ETD2RK steps, FP64): at 128^3 the fused launch takes
-// 26.6 us with 64 rows on 16 waves, 28.0 us with 32 rows on 8 waves and 29.0 us
+// Measured on MI355X (FP64): at 128^3 the fused launch takes 24.8 us with 64
+// rows on 16 waves and the interleaved chunk schedule ("r64w16i"), 26.0 us
+// without it, 27.2 / 28.5 us with 32 rows on 8 waves (with / without), 29.0 us
 // with 32 rows on 4 waves; at 80 x 81 x 82, where 64-row tiles give fewer
 // workgroups than CUs, 32 rows on 8 waves is fastest.
 // The autotuner's choice (or EXPINT_M12) comes first; its "not fused" candidate
@@ -262,7 +293,7 @@ constexpr int kNumShapes = sizeof(kRows) / sizeof(kRows[0]);
 int shape_choice(int n1, int n2, long r) {
   const int c = tune_choice(modes12_key(n1, n2, r));
   if (c >= 0 && c < kNumShapes) return c;
-  return (n1 + 63) / 64 * r >= 256 ? 4 : 1;
+  return (n1 + 63) / 64 * r >= 256 ? 8 : 6;
 }
 
 template <int NQ>
@@ -272,6 +303,10 @@ void launch_shape(int shape, long nt, hipStream_t st, const Modes12Args& g) {
     case 2: hipLaunchKernelGGL((k_modes12<NQ, 16, 1>), dim3((unsigned)nt), dim3(256), 0, st, g); break;
     case 3: hipLaunchKernelGGL((k_modes12<NQ, 64, 2>), dim3((unsigned)nt), dim3(512), 0, st, g); break;
     case 4: hipLaunchKernelGGL((k_modes12<NQ, 64, 4>), dim3((unsigned)nt), dim3(1024), 0, st, g); break;
+    case 5: hipLaunchKernelGGL((k_modes12<NQ, 32, 2, 1>), dim3((unsigned)nt), dim3(512), 0, st, g); break;
+    case 6: hipLaunchKernelGGL((k_modes12<NQ, 32, 2, 2>), dim3((unsigned)nt), dim3(512), 0, st, g); break;
+    case 7: hipLaunchKernelGGL((k_modes12<NQ, 64, 4, 1>), dim3((unsigned)nt), dim3(1024), 0, st, g); break;
+    case 8: hipLaunchKernelGGL((k_modes12<NQ, 64, 4, 2>), dim3((unsigned)nt), dim3(1024), 0, st, g); break;
     default: hipLaunchKernelGGL((k_modes12<NQ, 32, 1>), dim3((unsigned)nt), dim3(256), 0, st, g); break;
   }
 }

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -223,7 +224,8 @@ int tune_key(const TuneKey& k, void* stream, const std::function<int()>& launch)
   t_forced_choice = -1;
   if (rc != EXPINT_OK) return rc;
   const FullKey fk = full_key(k);
-  const Entry e{best, best_us};
+  // kept at the cache file's precision, so that this process and one that reads the file agree
+  const Entry e{best, std::round(best_us * 1e3) / 1e3};
   bool added = false;
   {
     std::lock_guard<std::mutex> lock(g_table_mutex);

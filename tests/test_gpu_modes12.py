@@ -95,7 +95,7 @@ def test_plan_steps_fused_equal_unfused(scheme, d, monkeypatch):
     assert rel_inf(out[0], out[1]) <= 1e-14
 
 
-@pytest.mark.parametrize("shape", ["r32w4", "r32w8", "r16w4", "r64w8", "r64w16"])
+@pytest.mark.parametrize("shape", ["r32w4", "r32w8", "r16w4", "r64w8", "r64w16", "r32w8p", "r32w8i", "r64w16p", "r64w16i"])
 @pytest.mark.parametrize("n", [(5, 3), (37, 70, 5), (40, 41, 42), (200, 128, 3), (4096, 3, 2)])
 def test_every_workgroup_shape(shape, n, monkeypatch):
     """Each workgroup shape of the fused launch (forced through EXPINT_M12)."""

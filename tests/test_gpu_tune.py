@@ -45,7 +45,7 @@ def _apply(n, seed, precision="fp64"):
 
 FP64_TILES = ["64x64", "64x32", "32x64", "128x64", "64x128", "32x32", "64x64w8", "128x64w8", "128x128w8",
               "128x128", "128x64w8k32", "128x128w8k32", "128x64w8p3", "128x64w8p4", "64x64w8p3", "64x64w8p4",
-              "64x64k32"]
+              "64x64k32", "128x64w8i", "64x64w8i"]
 
 
 def test_every_fp64_tile_gives_the_same_bits(monkeypatch):
@@ -62,7 +62,7 @@ def test_fused_and_unfused_modes12_give_the_same_bits(monkeypatch):
     n = (64, 96, 40)
     assert px.tucker_fuses_modes12(n)
     ref, V, Ms = _apply(n, 7)
-    for shape in ["r32w4", "r32w8", "r16w4", "r64w8", "r64w16", "off"]:
+    for shape in ["r32w4", "r32w8", "r16w4", "r64w8", "r64w16", "r32w8p", "r32w8i", "r64w16p", "r64w16i", "off"]:
         monkeypatch.setenv("EXPINT_M12", shape)
         got, _, _ = _apply(n, 7)
         assert torch.equal(got, ref), shape
