@@ -676,9 +676,9 @@ def tucker_roofline(args, p, px, dev, stream, U0, precision, workload):
             "traffic": traffic,
         }
     elif precision == "slice":
-        # one mode of tucker_apply: digits of the tensor (read 8 B, write 6 B per element),
-        # then the int8 GEMM (read 6 B, write 8 B per element); the digits of M are small
-        alg_bytes = 28 * p.N
+        # one mode of tucker_apply: digits of the tensor (read 8 B, write 5 B per element),
+        # then the int8 GEMM (read 5 B, write 8 B per element); the digits of M are small
+        alg_bytes = 26 * p.N
         hw_tops = SLICE_PRODUCTS * flops_per_launch / avg_launch_s / 1e12
         roofline = {"kernel": "k_slice_* + k_sliced_gemm (exact-slice mu-mode product, int8 MFMA)",
                     "bound": "mfma", "achieved": round(hw_tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
