@@ -5,6 +5,8 @@
 // writes its outputs once.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "device_common.h"
@@ -189,6 +191,163 @@ __global__ __launch_bounds__(kThreads) void k_stage_stencil_v(StencilArgs a) {
   for (int h = 0; h < V / 2; ++h) *reinterpret_cast<v2d*>(W + e0 + 2 * h) = v2d{w[2 * h], w[2 * h + 1]};
 }
 
+// Three directions, real data, n_1 a multiple of 64 and n_2 of 8: a 2.5-D
+// stencil.  A workgroup owns a 64 x 8 tile of (i_1, i_2) and a run of cz planes
+// i_3 = k0 .. k1 - 1, and streams along i_3.  A thread holds two consecutive
+// i_1 elements of one tile row and keeps their planes k - 1, k and k + 1 in
+// registers (the i_3 neighbours); plane k with a one-element halo in i_1 and
+// i_2 sits in LDS (the i_1 and i_2 neighbours), two buffers, one barrier per
+// plane.  So each element comes from memory once per workgroup (the halo rows
+// and columns, which the neighbouring tiles own, come mostly from L2), and
+// plane k + 2 is requested while plane k is computed.  Each element's terms are
+// summed in the same order as in k_stage_stencil, so the result is the same.
+constexpr int kS25X = 64, kS25Y = 8, kS25Z = 32;
+template <bool TOEP>
+__global__ __launch_bounds__(kThreads) void k_stage_stencil_25d(StencilArgs a, int cz) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  static_assert(kS25X * kS25Y == 2 * kThreads, "two elements per thread");
+  constexpr int LX = kS25X + 2, LY = kS25Y + 2;
+  constexpr int NH = 2 * kS25X + 2 * kS25Y;  // halo cells of a plane
+  __shared__ double buf[2][LY * LX];
+  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
+  const int ntx = n1 / kS25X, nty = n2 / kS25Y;
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+  const int x0 = tx * kS25X, y0 = ty * kS25Y;
+  const int k0 = tz * cz, k1 = min(n3, k0 + cz);
+  const int tid = threadIdx.x, lx = (tid & 31) * 2, ly = tid >> 5;
+  const int i1 = x0 + lx, i2 = y0 + ly;
+  const long plane = (long)n1 * n2;
+  const long orow = (long)i1 + (long)n1 * i2;
+  const bool per1 = a.periodic[0], per2 = a.periodic[1], per3 = a.periodic[2];
+  const double* U = static_cast<const double*>(a.U);
+  // plane k with the periodic wrap, or -1 past either end
+  auto pk = [&](int k) { return k < 0 ? (per3 ? k + n3 : -1) : (k >= n3 ? (per3 ? k - n3 : -1) : k); };
+  auto load_own = [&](int k, double (&v)[2]) {
+    const int kk = pk(k);
+    if (kk >= 0) {
+      const v2d t = *reinterpret_cast<const v2d*>(U + orow + plane * kk);
+      v[0] = t[0];
+      v[1] = t[1];
+    } else {
+      v[0] = 0.0;
+      v[1] = 0.0;
+    }
+  };
+  // halo cell of this thread: the rows above and below the tile, the columns
+  // left and right of it (none, or the periodic image, past the domain)
+  int hpos = -1;
+  long hoff = -1;
+  if (tid < NH) {
+    int yy, xx;
+    if (tid < kS25X) {
+      yy = 0;
+      xx = tid + 1;
+    } else if (tid < 2 * kS25X) {
+      yy = LY - 1;
+      xx = tid - kS25X + 1;
+    } else {
+      const int c = tid - 2 * kS25X;
+      yy = c % kS25Y + 1;
+      xx = c < kS25Y ? 0 : LX - 1;
+    }
+    int g1 = x0 + xx - 1, g2 = y0 + yy - 1;
+    bool ok = true;
+    if (g1 < 0 || g1 >= n1) {
+      ok = per1;
+      g1 = g1 < 0 ? g1 + n1 : g1 - n1;
+    }
+    if (g2 < 0 || g2 >= n2) {
+      ok = ok && per2;
+      g2 = g2 < 0 ? g2 + n2 : g2 - n2;
+    }
+    hpos = yy * LX + xx;
+    if (ok) hoff = (long)g1 + (long)n1 * g2;
+  }
+  auto load_halo = [&](int k) -> double {
+    const int kk = pk(k);
+    return (hoff >= 0 && kk >= 0) ? U[hoff + plane * kk] : 0.0;
+  };
+  const int me = (ly + 1) * LX + lx + 1;  // LDS position of the first own element
+  double p0[2], p1[2], p2[2], q[2];
+  load_own(k0 - 1, p0);
+  load_own(k0, p1);
+  load_own(k0 + 1, p2);
+  const double h0 = load_halo(k0);
+  double h1 = load_halo(k0 + 1);
+  buf[0][me] = p1[0];
+  buf[0][me + 1] = p1[1];
+  if (hpos >= 0) buf[0][hpos] = h0;
+  __syncthreads();
+  const double* c1 = static_cast<const double*>(a.coef[0]);
+  const double* c2 = static_cast<const double*>(a.coef[1]);
+  const double* c3 = static_cast<const double*>(a.coef[2]);
+  const bool lo2 = i2 > 0 || per2, up2 = i2 + 1 < n2 || per2;
+  const double clo2 = TOEP ? a.tc[1][0][0] : c2[i2];
+  const double cdi2 = TOEP ? a.tc[1][1][0] : c2[n2 + i2];
+  const double cup2 = TOEP ? a.tc[1][2][0] : c2[2 * n2 + i2];
+  const bool adr = a.g == EXPINT_G_ADR_PAPER;  // the only g that reads the device clock
+  const double now = adr ? clock_time(a.gt, 0.0) : 0.0;
+  double* W = static_cast<double*>(a.W);
+  for (int k = k0; k < k1; ++k) {
+    const int cb = (k - k0) & 1;
+    load_own(k + 2, q);
+    const double hq = load_halo(k + 2);
+    const double* L = buf[cb];
+    const bool lo3 = k > 0 || per3, up3 = k + 1 < n3 || per3;
+    const double clo3 = TOEP ? a.tc[2][0][0] : c3[k];
+    const double cdi3 = TOEP ? a.tc[2][1][0] : c3[n3 + k];
+    const double cup3 = TOEP ? a.tc[2][2][0] : c3[2 * n3 + k];
+    double w[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int j1 = i1 + v;
+      const double clo = TOEP ? a.tc[0][0][0] : c1[j1];
+      const double cdi = TOEP ? a.tc[0][1][0] : c1[n1 + j1];
+      const double cup = TOEP ? a.tc[0][2][0] : c1[2 * n1 + j1];
+      const double u = p1[v];
+      double acc = fma(cdi, u, 0.0);
+      if (j1 > 0 || per1) acc = fma(clo, L[me + v - 1], acc);
+      if (j1 + 1 < n1 || per1) acc = fma(cup, L[me + v + 1], acc);
+      acc = fma(cdi2, u, acc);
+      if (lo2) acc = fma(clo2, L[me + v - LX], acc);
+      if (up2) acc = fma(cup2, L[me + v + LX], acc);
+      acc = fma(cdi3, u, acc);
+      if (lo3) acc = fma(clo3, p0[v], acc);
+      if (up3) acc = fma(cup3, p2[v], acc);
+      const double gu = adr ? adr_paper_g(a.gt, u, now, j1, i2, k) : g_eval(a.g, u, a.gparam);
+      w[v] = (acc + gu) * a.tau;
+    }
+    *reinterpret_cast<v2d*>(W + orow + plane * k) = v2d{w[0], w[1]};
+    if (k + 1 < k1) {
+      double* N = buf[cb ^ 1];
+      N[me] = p2[0];
+      N[me + 1] = p2[1];
+      if (hpos >= 0) N[hpos] = h1;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      p0[v] = p1[v];
+      p1[v] = p2[v];
+      p2[v] = q[v];
+    }
+    h1 = hq;
+  }
+}
+
+// The 2.5-D stencil's run of planes per workgroup, or 0 where it does not apply
+// (it needs enough workgroups to fill the chip: at least four per CU).
+int stencil_25d_planes(const Stencil& st, int dtype) {
+  if (const char* e = std::getenv("EXPINT_STENCIL25"); e && std::strcmp(e, "0") == 0) return 0;
+  if (dtype != EXPINT_F64 || st.d != 3 || st.n[0] % kS25X != 0 || st.n[1] % kS25Y != 0) return 0;
+  const long tiles = (long)(st.n[0] / kS25X) * (st.n[1] / kS25Y);
+  const int cz = kS25Z;
+  const long wgs = tiles * ((st.n[2] + cz - 1) / cz);
+  if (const char* e = std::getenv("EXPINT_STENCIL25"); e && std::strcmp(e, "1") == 0) return cz;  // forced
+  return wgs >= 1024 ? cz : 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scaled_g(long N, const void* Uv, void* Wv, double s,
                                                        int g, double gp, GridTime gt) {
@@ -247,6 +406,15 @@ int launch_stage_stencil(int dtype, const Stencil& st, long N, const void* U, vo
   } else {                                                                                           \
     if (c) hipLaunchKernelGGL((k_stage_stencil<cdouble, D, false>), grid, block, 0, s, a);          \
     else hipLaunchKernelGGL((k_stage_stencil<double, D, false>), grid, block, 0, s, a);             \
+  }
+  // three directions, n_1 a multiple of 64, n_2 of 8, large enough: the 2.5-D kernel
+  if (const int cz = stencil_25d_planes(st, dtype); cz > 0) {
+    const long tiles = (long)(st.n[0] / kS25X) * (st.n[1] / kS25Y) * ((st.n[2] + cz - 1) / cz);
+    if (st.toeplitz)
+      hipLaunchKernelGGL((k_stage_stencil_25d<true>), dim3((unsigned)tiles), block, 0, s, a, cz);
+    else
+      hipLaunchKernelGGL((k_stage_stencil_25d<false>), dim3((unsigned)tiles), block, 0, s, a, cz);
+    return check_launch("stage_stencil_25d");
   }
   // real data with n_1 a multiple of 4 (or 2): the vectorised kernel
   const int V = c ? 1 : (st.n[0] % 4 == 0 ? 4 : (st.n[0] % 2 == 0 ? 2 : 1));
