@@ -318,8 +318,8 @@ typedef struct expint_batch_plan expint_batch_plan;
  * (section 1, eq. Riccati; Kronecker form eq. ODE2d), each integrated with
  * ETD2RK phisplit (section 3.2; for d = 2 the phi_2 stage carries the split
  * factor 2).  phi_1 and phi_2 of tau A1 and tau A2 are built once on the host
- * in FP64.  A step is ten GEMM phases; each phase is one persistent launch
- * over all instances, most expensive instances first.
+ * in FP64.  A step is ten GEMM phases; each phase is one grouped launch
+ * over all instances, each GEMM's tiles on one XCD, most expensive first.
  *   count   >= 1
  *   n1, n2  host arrays of count sizes, 1..4096
  *   A1, A2  host arrays of count host pointers, column-major n1 x n1 / n2 x n2 float64
@@ -374,8 +374,9 @@ int expint_batch_run(expint_batch_plan* plan, double* U, int nsteps, int use_gra
 /*
  * expint_batch_tune -- the autotuner for the batched engine: each step is a
  * fixed sequence of grouped launches (one per phase), and each launch can put
- * its GEMMs on one tile class (64 x 64 outputs) or on two classes in the same
- * persistent launch (128 x 64 or 128 x 128 outputs for the large GEMMs).  This
+ * its GEMMs on one tile class (64 x 64 or 128 x 64 outputs, with several K
+ * chunk depths and occupancies) or on two classes in the same launch (128 x 64
+ * outputs for the GEMMs with at least 128 rows, 64 x 64 for the rest).  This
  * times every grouped tile scheme on every phase, starting from one step of a
  * private copy of U (device, packed state, left unchanged; ws as for
  * expint_batch_step), and keeps the fastest per phase for the rest of the

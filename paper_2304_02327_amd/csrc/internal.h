@@ -146,11 +146,11 @@ bool modes12_fits(int n1, int n2);
 int launch_modes12(int n1, int n2, long r, const void* M1, const void* M2, const void* V, const Epilogue& epi,
                    void* stream);
 
-// Grouped FP64 GEMMs in one persistent launch (batched instances).  A
-// descriptor describes C[m, q] = sum_k A[m + lda k] B[k bk + q bq] for
-// m < M, q < Q, k < K with output element m + ldc q and an epilogue;
-// bk == 1 (B contiguous along k) or bq == 1 (contiguous along q) selects the
-// kernel.  `start` (device, count + 1 entries) holds the tile prefix sums.
+// Grouped FP64 GEMMs in one launch (batched instances).  A descriptor
+// describes C[m, q] = sum_k A[m + lda k] B[k bk + q bq] for m < M, q < Q,
+// k < K with output element m + ldc q and an epilogue; bk == 1 (B contiguous
+// along k) or bq == 1 (contiguous along q) selects the kernel.  A workgroup map
+// (grouped_block_map) assigns the tiles to the workgroups.
 size_t gemm_desc_size();
 // gate (device int, optional): the descriptor's tiles run only while *gate > gate_level
 int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, long bq, long M, long Q, long K,

@@ -93,7 +93,7 @@ __shared__ double lds_pool[N];
 // One TM x TQ output tile (tile index T_ in [0, tiles_m tiles_q batches)) of the
 // GEMM described by g, computed by the whole workgroup in lds_pool<LDSN>
 // (at least tile_lds_doubles entries).  Used by the single launch below and by
-// the persistent grouped launch, whose tile classes share one LDS allocation.
+// the grouped launch, whose tile classes share one LDS allocation.
 // IL: in the steady-state loop each chunk's MFMAs are interleaved with its LDS
 // reads, LDS writes and global loads (scheduling groups) instead of the
 // compiler's own order.
@@ -332,8 +332,9 @@ __global__ __launch_bounds__(64 * WGM * WGQ) void k_mode_product(GemmArgs g) {
       g, xcd_remap((long)blockIdx.x, nt));
 }
 
-// Tile classes of the persistent grouped launch: TM x TQ outputs, K chunks of
-// KC, WGM x WGQ waves (512 threads in every class).
+// Tile classes of the grouped launch: TM x TQ outputs, K chunks of KC, WGM x WGQ
+// waves (both classes of a launch on the same thread count), registers for WPE
+// waves per SIMD.
 template <int TM_, int TQ_, int KC_, int WGM_, int WGQ_, int WPE_ = 4, bool IL_ = false>
 struct TileCfg {
   static constexpr int TM = TM_, TQ = TQ_, KC = KC_, WGM = WGM_, WGQ = WGQ_, NT = 64 * WGM_ * WGQ_;

@@ -5,8 +5,8 @@
 // K = I (x) A1 + A2 (x) I, so K u = A1 U + U A2^T and a Tucker operator is
 // M1 W M2^T).  One ETD2RK step (section 3.2, eq. ETD2RKtensor read with the
 // split factor (2!)^{d-1} = 2 and tau on the whole first bracket) is ten
-// GEMM phases; each phase is one persistent grouped launch over all
-// instances, longest first:
+// GEMM phases; each phase is one grouped launch over all instances (each
+// GEMM's tiles on one XCD, longest first):
 //    1  T  = U B          (n1 <= n2)   or   B U   (n2 < n1)
 //    2  Gn = C + T U                   or   C + U T
 //    3  W  = tau A1 U + tau Gn
