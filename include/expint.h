@@ -318,7 +318,7 @@ typedef struct expint_batch_plan expint_batch_plan;
  * (section 1, eq. Riccati; Kronecker form eq. ODE2d), each integrated with
  * ETD2RK phisplit (section 3.2; for d = 2 the phi_2 stage carries the split
  * factor 2).  phi_1 and phi_2 of tau A1 and tau A2 are built once on the host
- * in FP64.  A step is ten GEMM phases; each phase is one grouped launch
+ * in FP64.  A step is nine GEMM phases; each phase is one grouped launch
  * over all instances, each GEMM's tiles on one XCD, most expensive first.
  *   count   >= 1
  *   n1, n2  host arrays of count sizes, 1..4096

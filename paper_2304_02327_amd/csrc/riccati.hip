@@ -4,19 +4,21 @@
 // (paper section 1, eq. Riccati; Kronecker form eq. ODE2d with
 // K = I (x) A1 + A2 (x) I, so K u = A1 U + U A2^T and a Tucker operator is
 // M1 W M2^T).  One ETD2RK step (section 3.2, eq. ETD2RKtensor read with the
-// split factor (2!)^{d-1} = 2 and tau on the whole first bracket) is ten
+// split factor (2!)^{d-1} = 2 and tau on the whole first bracket) is nine
 // GEMM phases; each phase is one grouped launch over all instances (each
 // GEMM's tiles on one XCD, longest first):
-//    1  T  = U B          (n1 <= n2)   or   B U   (n2 < n1)
+//    1  T  = U B          (n1 <= n2)   or   B U   (n2 < n1),   and  W = tau U A2^T
 //    2  Gn = C + T U                   or   C + U T
-//    3  W  = tau A1 U + tau Gn
-//    4  W  = W + tau U A2^T
-//    5  P  = phi1(tau A1) W
-//    6  U2 = U + P phi1(tau A2)^T
-//    7  T  = U2 B                      or   B U2
-//    8  W2 = tau (T U2 + C - Gn)       or   tau (U2 T + C - Gn)
-//    9  P  = phi2(tau A1) W2
-//   10  U  = U2 + 2 P phi2(tau A2)^T
+//    3  W  = tau A1 U + W + tau Gn
+//    4  P  = phi1(tau A1) W
+//    5  U2 = U + P phi1(tau A2)^T
+//    6  T  = U2 B                      or   B U2
+//    7  W2 = tau (T U2 + C - Gn)       or   tau (U2 T + C - Gn)
+//    8  P  = phi2(tau A1) W2
+//    9  U  = U2 + 2 P phi2(tau A2)^T
+// (the two products of phase 1 depend on U alone; U A2^T reads the stored
+// transpose of A2, so that every product of the phase has its B operand
+// contiguous along k).
 // The association of U B U is chosen per instance so the middle product is
 // min(n1, n2) square.
 //
@@ -29,7 +31,7 @@
 //    U <- U + phi_1(X1) W phi_1(X2),   W = tau f(U) = tau A1 U + tau C + U X2
 // (U X2 = tau U A2^T + tau U B U).  The phases:
 //    R1  X1 = tau (A1 + U B),  X2 = tau (A2^T + B U)
-//    R2  W  = tau A1 U + tau C
+//    R2  W  = tau A1 U + tau C               (one launch with R1: both read U alone)
 //    R3  W  = W + U X2
 //        k_phi_prep: s = the even power of two with ||X / 2^s||_1 <= 1/2,
 //        Y = X / 2^s, H = Y / 14! + I / 13!
@@ -58,7 +60,8 @@ using namespace expint;
 
 namespace {
 
-constexpr int kPhases = 10;  // ETD2RK
+constexpr int kPhases = 9;  // ETD2RK
+constexpr int kEtdDescs = 10;  // ETD2RK descriptors per instance and step (phase 1 has two)
 constexpr int kHorner = 12;  // Rosenbrock-Euler: Horner GEMM steps after the prep kernel
 
 // One matrix of the per-step phi_1 of the Rosenbrock-Euler scheme.
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(64 * kPrepWaves) void k_phi_prep(const PhiJob* __re
 }
 
 // ETD2RK phases whose B operand is contiguous along k (the others read M^T, contiguous along q)
-constexpr bool kPhaseBK[kPhases] = {true, true, true, false, true, false, true, true, true, false};
+constexpr bool kPhaseBK[kPhases] = {true, true, true, true, false, true, true, true, false};
 
 }  // namespace
 
@@ -154,7 +157,7 @@ struct expint_batch_plan {
   double* dA2 = nullptr;      // A2, phi1(tau A2), phi2(tau A2) (each m2total)
   double* dP1b = nullptr;
   double* dP2b = nullptr;
-  double* dA2T = nullptr;     // Rosenbrock-Euler: A2^T (m2total)
+  double* dA2T = nullptr;     // A2^T (m2total)
   int scheme = EXPINT_ETD2RK;
   int smax = 0;               // Rosenbrock-Euler: squaring phases per step
   std::vector<int> morder;    // Rosenbrock-Euler: the 2 count matrices by decreasing size
@@ -265,7 +268,7 @@ struct PhaseBuilder {
   }
 };
 
-// ETD2RK: the ten phases listed at the top of this file.
+// ETD2RK: the nine phases listed at the top of this file.
 void build_etd2rk(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb) {
   const int cnt = p->count;
   double* T = reinterpret_cast<double*>(ws);
@@ -289,46 +292,48 @@ void build_etd2rk(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb) {
       double* Ti = T + to;
       double *Gi = Gn + uo, *Wi = W + uo, *Pi = P + uo, *W2i = W2 + uo;
       const double *A1 = p->dA1 + p->moff1[i], *P1a = p->dP1a + p->moff1[i], *P2a = p->dP2a + p->moff1[i];
-      const double *A2 = p->dA2 + p->moff2[i], *P1b = p->dP1b + p->moff2[i], *P2b = p->dP2b + p->moff2[i];
-      char* d = pb.add();
-      const double* Us = (ph < 6) ? Ui : U2i;  // state the phase reads (phases 7, 8 use U2)
+      const double *A2T = p->dA2T + p->moff2[i], *P1b = p->dP1b + p->moff2[i], *P2b = p->dP2b + p->moff2[i];
       switch (ph) {
-        case 0:
-        case 6:  // T = U B  or  B U
+        case 0:  // T = U B  or  B U;  W = tau U A2^T  (B operand A2^T[k, q] = A2T[k + n2 q])
           if (left)
-            make_gemm_desc(d, Us, n1, Bi, 1, n2, n1, n1, n2, n1, linear(Ti, 1.0));
+            make_gemm_desc(pb.add(), Ui, n1, Bi, 1, n2, n1, n1, n2, n1, linear(Ti, 1.0));
           else
-            make_gemm_desc(d, Bi, n2, Us, 1, n1, n2, n2, n1, n2, linear(Ti, 1.0));
+            make_gemm_desc(pb.add(), Bi, n2, Ui, 1, n1, n2, n2, n1, n2, linear(Ti, 1.0));
+          pb.added();
+          make_gemm_desc(pb.add(), Ui, n1, A2T, 1, n2, n1, n2, n2, n1, linear(Wi, tau));
+          break;
+        case 5:  // T = U2 B  or  B U2
+          if (left)
+            make_gemm_desc(pb.add(), U2i, n1, Bi, 1, n2, n1, n1, n2, n1, linear(Ti, 1.0));
+          else
+            make_gemm_desc(pb.add(), Bi, n2, U2i, 1, n1, n2, n2, n1, n2, linear(Ti, 1.0));
           break;
         case 1:  // Gn = C + T U  or  C + U T
           if (left)
-            make_gemm_desc(d, Ti, n1, Ui, 1, n1, n1, n2, n1, n1, linear(Gi, 1.0, Ci, 1.0));
+            make_gemm_desc(pb.add(), Ti, n1, Ui, 1, n1, n1, n2, n1, n1, linear(Gi, 1.0, Ci, 1.0));
           else
-            make_gemm_desc(d, Ui, n1, Ti, 1, n2, n1, n2, n2, n1, linear(Gi, 1.0, Ci, 1.0));
+            make_gemm_desc(pb.add(), Ui, n1, Ti, 1, n2, n1, n2, n2, n1, linear(Gi, 1.0, Ci, 1.0));
           break;
-        case 7:  // W2 = tau (T U2 + C - Gn)  or  tau (U2 T + C - Gn)
+        case 6:  // W2 = tau (T U2 + C - Gn)  or  tau (U2 T + C - Gn)
           if (left)
-            make_gemm_desc(d, Ti, n1, U2i, 1, n1, n1, n2, n1, n1, linear(W2i, tau, Ci, tau, Gi, -tau));
+            make_gemm_desc(pb.add(), Ti, n1, U2i, 1, n1, n1, n2, n1, n1, linear(W2i, tau, Ci, tau, Gi, -tau));
           else
-            make_gemm_desc(d, U2i, n1, Ti, 1, n2, n1, n2, n2, n1, linear(W2i, tau, Ci, tau, Gi, -tau));
+            make_gemm_desc(pb.add(), U2i, n1, Ti, 1, n2, n1, n2, n2, n1, linear(W2i, tau, Ci, tau, Gi, -tau));
           break;
-        case 2:  // W = tau A1 U + tau Gn
-          make_gemm_desc(d, A1, n1, Ui, 1, n1, n1, n2, n1, n1, linear(Wi, tau, Gi, tau));
+        case 2:  // W = tau A1 U + W + tau Gn
+          make_gemm_desc(pb.add(), A1, n1, Ui, 1, n1, n1, n2, n1, n1, linear(Wi, tau, Wi, 1.0, Gi, tau));
           break;
-        case 3:  // W += tau U A2^T   (B operand A2^T[k, q] = A2[q + n2 k])
-          make_gemm_desc(d, Ui, n1, A2, n2, 1, n1, n2, n2, n1, linear(Wi, tau, Wi, 1.0));
+        case 3:  // P = phi1(tau A1) W
+          make_gemm_desc(pb.add(), P1a, n1, Wi, 1, n1, n1, n2, n1, n1, linear(Pi, 1.0));
           break;
-        case 4:  // P = phi1(tau A1) W
-          make_gemm_desc(d, P1a, n1, Wi, 1, n1, n1, n2, n1, n1, linear(Pi, 1.0));
+        case 4:  // U2 = U + P phi1(tau A2)^T
+          make_gemm_desc(pb.add(), Pi, n1, P1b, n2, 1, n1, n2, n2, n1, linear(U2i, 1.0, Ui, 1.0));
           break;
-        case 5:  // U2 = U + P phi1(tau A2)^T
-          make_gemm_desc(d, Pi, n1, P1b, n2, 1, n1, n2, n2, n1, linear(U2i, 1.0, Ui, 1.0));
+        case 7:  // P = phi2(tau A1) W2
+          make_gemm_desc(pb.add(), P2a, n1, W2i, 1, n1, n1, n2, n1, n1, linear(Pi, 1.0));
           break;
-        case 8:  // P = phi2(tau A1) W2
-          make_gemm_desc(d, P2a, n1, W2i, 1, n1, n1, n2, n1, n1, linear(Pi, 1.0));
-          break;
-        case 9:  // U = U2 + 2 P phi2(tau A2)^T
-          make_gemm_desc(d, Pi, n1, P2b, n2, 1, n1, n2, n2, n1, linear(Ui, 2.0, U2i, 1.0));
+        case 8:  // U = U2 + 2 P phi2(tau A2)^T
+          make_gemm_desc(pb.add(), Pi, n1, P2b, n2, 1, n1, n2, n2, n1, linear(Ui, 2.0, U2i, 1.0));
           break;
       }
       pb.added();
@@ -363,8 +368,7 @@ void build_rosenbrock(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& p
                    linear(mat(cnt + i, 0), tau, p->dA2T + p->moff2[i], tau));
     pb.added();
   }
-  // R2: W = tau A1 U + tau C
-  pb.open(true);
+  // R2: W = tau A1 U + tau C (in the launch of R1: both read U alone)
   for (int slot = 0; slot < cnt; ++slot) {
     const int i = p->order[slot];
     const long n1 = p->n1[i], n2 = p->n2[i], uo = p->uoff[i];
@@ -450,7 +454,7 @@ void build_rosenbrock(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& p
 int build_phases(expint_batch_plan* p, double* U, char* ws, PhaseBuilder& pb, std::vector<PhiJob>& jobs) {
   if (p->scheme == EXPINT_ROSENBROCK_EULER) {
     build_rosenbrock(p, U, ws, pb, jobs);
-    p->prep_after = 2;
+    p->prep_after = 1;
   } else {
     build_etd2rk(p, U, ws, pb);
     p->prep_after = -1;
@@ -642,23 +646,29 @@ int riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const
   };
   upload(&p->dA1, hA1);
   upload(&p->dA2, hA2);
+  {
+    // A2^T (column-major n2 x n2 per instance): the B operand of U A2^T contiguous along k
+    std::vector<double> hA2T(p->m2total);
+    for (int i = 0; i < count; ++i) {
+      const long m = n2[i];
+      for (long r = 0; r < m; ++r)
+        for (long c = 0; c < m; ++c) hA2T[p->moff2[i] + r + m * c] = A2[i][c + m * r];
+    }
+    upload(&p->dA2T, hA2T);
+  }
   size_t ndesc = 0;
   if (!ros) {
     upload(&p->dP1a, hP1a);
     upload(&p->dP2a, hP2a);
     upload(&p->dP1b, hP1b);
     upload(&p->dP2b, hP2b);
-    ndesc = (size_t)kPhases * count;
+    ndesc = (size_t)kEtdDescs * count;
   } else {
-    // A2^T, the matrices by decreasing size, and the number of squaring phases:
-    // the largest count ||tau A_mu||_1 needs, plus 4 for the U B terms of the
+    // the matrices by decreasing size, and the number of squaring phases: the
+    // largest count ||tau A_mu||_1 needs, plus 4 for the U B terms of the
     // Jacobian (a matrix needing more is squared that many times only)
-    std::vector<double> hA2T(p->m2total);
     double numax = 0.0;
     for (int i = 0; i < count; ++i) {
-      const long m = n2[i];
-      for (long r = 0; r < m; ++r)
-        for (long c = 0; c < m; ++c) hA2T[p->moff2[i] + r + m * c] = A2[i][c + m * r];
       for (int dir = 0; dir < 2; ++dir) {
         const long n = dir ? n2[i] : n1[i];
         const double* A = dir ? A2[i] : A1[i];
@@ -675,7 +685,6 @@ int riccati_plan_create(expint_batch_plan** out, int count, const int* n1, const
       ++sc;
     }
     p->smax = sc + 4 + ((sc + 4) & 1);
-    upload(&p->dA2T, hA2T);
     p->morder.resize(2 * count);
     std::iota(p->morder.begin(), p->morder.end(), 0);
     std::stable_sort(p->morder.begin(), p->morder.end(), [&](int a, int b) {
@@ -906,7 +915,7 @@ extern "C" int expint_batch_describe(const expint_batch_plan* p, char* buf, size
   if (!p) return set_error(EXPINT_EINVAL, "plan is NULL");
   std::string text;
   try {
-    const int nph = p->scheme == EXPINT_ROSENBROCK_EULER ? 18 + p->smax : kPhases;
+    const int nph = p->scheme == EXPINT_ROSENBROCK_EULER ? 17 + p->smax : kPhases;
     for (int k = 0; k < nph; ++k) {
       const TuneKey key = grouped_key(p, k);
       const int c = tune_choice(key);

@@ -89,6 +89,6 @@ def test_tuned_plan_leaves_the_state_and_matches_untuned(scheme, monkeypatch):
     monkeypatch.delenv("EXPINT_GROUPED")
     out, got, text = _run(insts, scheme, 2, tune=True)
     lines = text.splitlines()
-    assert len(lines) >= 10 and all("tuned" in l for l in lines), text
+    assert len(lines) >= 9 and all("tuned" in l for l in lines), text
     assert all(l.split(": ")[1].split(" ")[0] in SCHEMES for l in lines), text
     assert torch.equal(out, ref)

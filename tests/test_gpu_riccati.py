@@ -1,7 +1,7 @@
 """Batched Riccati instances (persistent grouped GEMM launches) against the oracle.
 
 Each instance U' = A1 U + U A2^T + C + U B U is stepped with ETD2RK phisplit by
-the library (ten grouped GEMM phases per step) and, independently, by the
+the library (nine grouped GEMM phases per step) and, independently, by the
 oracle's tensor-form ETD2RK with g = C + U B U.  Bar: relative max-norm error
 <= 1e-12 per instance (FP64 throughout).
 """
