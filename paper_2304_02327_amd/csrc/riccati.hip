@@ -518,7 +518,13 @@ int prepare(expint_batch_plan* p, double* U, void* ws) {
   if (!U || !ws) return set_error(EXPINT_EINVAL, "U and ws must be non-NULL device pointers");
   if ((reinterpret_cast<uintptr_t>(U) & 15u) || (reinterpret_cast<uintptr_t>(ws) & 15u))
     return set_error(EXPINT_EINVAL, "U and ws must be 16-byte aligned");
-  if (p->d_U != U || p->d_ws != ws) return build_descriptors(p, U, static_cast<char*>(ws));
+  if (p->d_U != U || p->d_ws != ws) {
+    try {  // host vectors and the tuning table: nothing may throw across the C ABI
+      return build_descriptors(p, U, static_cast<char*>(ws));
+    } catch (...) {
+      return set_error(EXPINT_ENOMEM, "host resources exhausted while building the batched descriptors");
+    }
+  }
   return EXPINT_OK;
 }
 
@@ -906,8 +912,8 @@ extern "C" int expint_batch_tune(expint_batch_plan* p, double* U, void* ws, void
     return set_error(EXPINT_EINVAL, "U and ws must be 16-byte aligned");
   try {
     return batch_tune(p, U, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
-  } catch (const std::bad_alloc&) {
-    return set_error(EXPINT_ENOMEM, "host allocation failed while tuning the batched plan");
+  } catch (...) {
+    return set_error(EXPINT_ENOMEM, "host resources exhausted while tuning the batched plan");
   }
 }
 
@@ -922,8 +928,8 @@ extern "C" int expint_batch_describe(const expint_batch_plan* p, char* buf, size
       text += "phase " + std::to_string(k + 1) + ": " + grouped_scheme_name(std::max(0, c)) + " [" +
               tune_describe(key) + "]\n";
     }
-  } catch (const std::bad_alloc&) {
-    return set_error(EXPINT_ENOMEM, "host allocation failed while describing the batched plan");
+  } catch (...) {
+    return set_error(EXPINT_ENOMEM, "host resources exhausted while describing the batched plan");
   }
   if (needed) *needed = text.size() + 1;
   if (buf && len > 0) {
