@@ -165,8 +165,9 @@ void gemm_desc_set_scheme(void* desc, int scheme);
 struct GroupedBlock {
   int desc, tile;
 };
-// The map of `count` consecutive descriptors (host): each GEMM's tiles on one XCD.
-void grouped_block_map(const void* descs, int count, std::vector<GroupedBlock>& map);
+// The map of `count` consecutive descriptors (host) under a grouped scheme: each
+// GEMM's tiles on one XCD, balanced by the scheme's work measure.
+void grouped_block_map(const void* descs, int count, int scheme, std::vector<GroupedBlock>& map);
 bool grouped_block_map_valid(const void* descs, int count, const std::vector<GroupedBlock>& map);
 // descs and map (blocks entries) in device memory; every descriptor follows `scheme`.
 int launch_grouped_gemm(bool bk_contiguous, const void* descs, const GroupedBlock* map, long blocks, int scheme,

@@ -469,9 +469,17 @@ TuneKey mode_product_key(bool cplx, long s, int n, long r) {
 //   "64x64k16+128x64k8"  GEMMs with M >= 128 on 128 x 64 tiles (K chunks of 8), the rest 64 x 64 (16)
 // The two-class schemes serve both classes from one launch and one LDS
 // allocation.  EXPINT_GROUPED set to one of these names overrides the tuned choice.
-const char* const kGroupedNames[] = {"64x64k16", "64x64k16o4", "64x64",        "64x64w4",
-                                     "128x64",   "128x64k8",   "64x64+128x64", "64x64k16+128x64k8"};
+// Each tile scheme comes with two workgroup maps (grouped_block_map): balanced by
+// multiply-adds (the name alone) or with a per-tile allowance for the prologue and
+// epilogue and finer runs (the name with ",lpt64").
+const char* const kGroupedNames[] = {"64x64k16",           "64x64k16o4",           "64x64",
+                                     "64x64w4",            "128x64",               "128x64k8",
+                                     "64x64+128x64",       "64x64k16+128x64k8",    "64x64k16,lpt64",
+                                     "64x64k16o4,lpt64",   "64x64,lpt64",          "64x64w4,lpt64",
+                                     "128x64,lpt64",       "128x64k8,lpt64",       "64x64+128x64,lpt64",
+                                     "64x64k16+128x64k8,lpt64"};
 constexpr int kNumGrouped = sizeof(kGroupedNames) / sizeof(kGroupedNames[0]);
+constexpr int kNumTileSchemes = kNumGrouped / 2;
 
 int grouped_scheme_count() { return kNumGrouped; }
 const char* grouped_scheme_name(int i) { return i >= 0 && i < kNumGrouped ? kGroupedNames[i] : "?"; }
@@ -480,7 +488,7 @@ const char* grouped_scheme_name(int i) { return i >= 0 && i < kNumGrouped ? kGro
 static int grouped_class(int scheme, long M, long Q, int* tm, int* tq) {
   (void)Q;
   int cls = 0;
-  switch (scheme) {
+  switch (scheme % kNumTileSchemes) {
     case 4:
     case 5: cls = 1; break;
     case 6:
@@ -510,7 +518,7 @@ static void launch_grouped_typed(long grid, const GemmArgs* d, const GroupedBloc
 
 template <bool BK>
 static void launch_grouped_scheme(int scheme, long grid, const GemmArgs* d, const GroupedBlock* map, hipStream_t st) {
-  switch (scheme) {
+  switch (scheme % kNumTileSchemes) {
     case 1: return launch_grouped_typed<BK, GSmall16x, GSmall16x>(grid, d, map, st);
     case 2: return launch_grouped_typed<BK, GSmall, GSmall>(grid, d, map, st);
     case 3: return launch_grouped_typed<BK, GSmall4, GSmall4>(grid, d, map, st);
@@ -569,14 +577,16 @@ int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, l
 // The workgroup -> tile map of a grouped launch.  Workgroups are dispatched to
 // the XCDs in turn (b mod 8), and each XCD has its own L2, so the tiles of one
 // GEMM, which re-read each other's operand panels, are kept on one XCD: the
-// GEMMs (split into runs of at most a sixteenth of all tiles, so that no XCD
+// GEMMs (split into runs of at most an eighth of all tiles, so that no XCD
 // holds much more than its share) go to the XCDs longest first, each to the
-// XCD with the least work so far (work = tiles x TM TQ (K + 64), the 64
-// standing for the prologue and the epilogue); within an XCD the runs keep
-// that order.  XCD x's j-th tile becomes workgroup 8 j + x; a workgroup past
+// XCD with the least work so far (work = tiles x TM TQ K); within an XCD the
+// runs keep that order.  The ",lpt64" schemes add 64 to K for each tile's
+// prologue and epilogue and cut runs at a sixteenth (measured on the
+// 64-instance batch: ETD2RK 0.71 ms per step with the first measure against
+// 0.74 with the second, Rosenbrock-Euler the other way round, 7.36 against 7.53).  XCD x's j-th tile becomes workgroup 8 j + x; a workgroup past
 // the end of its XCD's list has desc = -1.  EXPINT_GROUPED_FLAT=1 gives the
 // plain order (tile t on workgroup t) instead.
-void grouped_block_map(const void* descs, int count, std::vector<GroupedBlock>& map) {
+void grouped_block_map(const void* descs, int count, int scheme, std::vector<GroupedBlock>& map) {
   constexpr int X = 8;
   const GemmArgs* d = static_cast<const GemmArgs*>(descs);
   std::vector<long> tiles(count);
@@ -598,12 +608,13 @@ void grouped_block_map(const void* descs, int count, std::vector<GroupedBlock>& 
     long t0, t1;
     double work;
   };
-  const long cap = std::max(1L, (total + 15) / 16);
+  const bool lpt64 = scheme >= kNumTileSchemes;
+  const long cap = lpt64 ? std::max(1L, (total + 15) / 16) : std::max(1L, (total + 7) / 8);
   std::vector<Run> runs;
   for (int i = 0; i < count; ++i) {
     GemmArgs g;
     std::memcpy(&g, d + i, sizeof(g));
-    const double per = (double)g.tile_m * g.tile_q * (double)(g.K + 64);
+    const double per = (double)g.tile_m * g.tile_q * (double)(g.K + (lpt64 ? 64 : 0));
     for (long t0 = 0; t0 < tiles[i]; t0 += cap) {
       const long t1 = std::min(tiles[i], t0 + cap);
       runs.push_back(Run{i, t0, t1, per * (double)(t1 - t0)});

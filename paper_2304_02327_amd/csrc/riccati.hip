@@ -258,7 +258,7 @@ struct PhaseBuilder {
   bool finish() {  // every phase's workgroup map, after the last descriptor
     std::vector<GroupedBlock> m;
     for (auto& ph : phases) {
-      grouped_block_map(desc.data() + (size_t)ph.first * dsz, ph.ndesc, m);
+      grouped_block_map(desc.data() + (size_t)ph.first * dsz, ph.ndesc, ph.scheme, m);
       if (!grouped_block_map_valid(desc.data() + (size_t)ph.first * dsz, ph.ndesc, m)) return false;
       ph.map_off = (long)map.size();
       ph.blocks = (long)m.size();

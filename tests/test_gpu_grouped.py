@@ -22,8 +22,9 @@ from oracle.norms import rel_inf
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = ["64x64k16", "64x64k16o4", "64x64", "64x64w4", "128x64", "128x64k8", "64x64+128x64",
-           "64x64k16+128x64k8"]
+TILES = ["64x64k16", "64x64k16o4", "64x64", "64x64w4", "128x64", "128x64k8", "64x64+128x64",
+         "64x64k16+128x64k8"]
+SCHEMES = TILES + [t + ",lpt64" for t in TILES]  # each tile scheme with both workgroup maps
 
 
 def _instances(seed=41):
