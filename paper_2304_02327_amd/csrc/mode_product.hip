@@ -583,9 +583,10 @@ int make_gemm_desc(void* out, const void* A, long lda, const void* B, long bk, l
 // runs keep that order.  The ",lpt64" schemes add 64 to K for each tile's
 // prologue and epilogue and cut runs at a sixteenth (measured on the
 // 64-instance batch: ETD2RK 0.71 ms per step with the first measure against
-// 0.74 with the second, Rosenbrock-Euler the other way round, 7.36 against 7.53).  XCD x's j-th tile becomes workgroup 8 j + x; a workgroup past
-// the end of its XCD's list has desc = -1.  EXPINT_GROUPED_FLAT=1 gives the
-// plain order (tile t on workgroup t) instead.
+// 0.74 with the second, Rosenbrock-Euler the other way round, 7.36 against
+// 7.53).  XCD x's j-th tile becomes workgroup 8 j + x; a workgroup past the end
+// of its XCD's list has desc = -1.  EXPINT_GROUPED_FLAT=1 gives the plain order
+// (tile t on workgroup t) instead.
 void grouped_block_map(const void* descs, int count, int scheme, std::vector<GroupedBlock>& map) {
   constexpr int X = 8;
   const GemmArgs* d = static_cast<const GemmArgs*>(descs);
