@@ -257,8 +257,7 @@ def bench_riccati(args, scheme="etd2rk"):
     if not args.no_cpu_baseline:
         from oracle import nonlinear, schemes
         from oracle.norms import rel_inf
-        sample = list(range(0, 64, 8))  # 8 of the 64 instances
-        k = 3
+        sample = list(range(0, 64, 2))  # 32 of the 64 instances
         t = time.perf_counter()
         integs = []
         for i in sample:
@@ -267,12 +266,20 @@ def bench_riccati(args, scheme="etd2rk"):
             if not ros:
                 integs.append(schemes.Integrator([x.A1, x.A2], tau, "etd2rk", g))
         osetup = time.perf_counter() - t
+
+        def oracle_run(steps):
+            if ros:
+                return [schemes.run_rosenbrock_euler_riccati(insts[i].U0, tau, steps, insts[i].A1, insts[i].A2,
+                                                             insts[i].B, insts[i].C) for i in sample]
+            return [integ.run(insts[i].U0, 0.0, steps) for integ, i in zip(integs, sample)]
+
+        # the number of steps from one timed step: about --cpu-seconds / 2 of CPU work, 2 .. 500 steps
         t = time.perf_counter()
-        if ros:
-            outs = [schemes.run_rosenbrock_euler_riccati(insts[i].U0, tau, k, insts[i].A1, insts[i].A2, insts[i].B,
-                                                          insts[i].C) for i in sample]
-        else:
-            outs = [integ.run(insts[i].U0, 0.0, k) for integ, i in zip(integs, sample)]
+        oracle_run(1)
+        one = time.perf_counter() - t
+        k = int(max(2, min(500, 0.5 * args.cpu_seconds / max(one, 1e-3))))
+        t = time.perf_counter()
+        outs = oracle_run(k)
         secs = time.perf_counter() - t
         Ug = U0.clone()
         batch.run(Ug, k)
@@ -280,9 +287,14 @@ def bench_riccati(args, scheme="etd2rk"):
         got = batch.state_from_device(Ug)
         err = max(rel_inf(got[i], o) for i, o in zip(sample, outs))
         dof = sum(insts[i].n1 * insts[i].n2 for i in sample)
-        result["cpu_baseline"] = {"value": dof * k / secs, "unit": "DOF-steps/s", "cores": os.cpu_count(),
-                                  "kind": "oracle", "sample": f"{k} steps of instances {sample} (oracle phi setup "
-                                  f"{osetup:.1f} s excluded)", "seconds": round(secs, 3),
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        result["cpu_baseline"] = {"value": dof * k / secs, "unit": "DOF-steps/s", "cores": cores,
+                                  "kind": "oracle", "sample": f"{k} steps of the even-numbered 32 of the 64 "
+                                  f"instances (oracle phi setup {osetup:.1f} s excluded)", "seconds": round(secs, 3),
                                   "gpu_vs_oracle_rel_inf": err}
     batch.close()
     print(json.dumps(result))
